@@ -1,0 +1,256 @@
+"""Benchmark of the dense state-vector hot path on one MI355X.
+
+One step = the whole path on the 30-qubit depth-40 layered random circuit
+(1200 U3 + 580 CZ, seed 30) in complex64:
+  init |0>  ->  planned gate passes  ->  probability vector (FP32, device)
+  ->  marginal of the top 10 qubits  ->  10^6 samples.
+Inputs are synthetic and generated before the timed region; the state stays
+resident in HBM.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("gate-pass HBM GB/s (% of peak), 30q depth-40 time; "
+          "batched circuits/s, p99")
+PEAK_HBM_GBPS = 8000.0
+N_QUBITS, DEPTH, SEED = 30, 40, 30
+SHOTS, SAMPLE_SEED = 1_000_000, 1000003
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_kernel_30q_c64_traffic.json")
+TILE_SRC = os.path.join(ROOT, "paper_2502_11385_amd", "csrc", "k_tile.hip")
+
+
+def _src_hash(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+# --------------------------------------------------------------- CPU leg
+
+def cpu_baseline_leg(budget_s: float) -> dict:
+    """The oracle (complex128 NumPy, one thread) on a bounded prefix of the
+    20-qubit instance of the same construction and seed; rate in the same
+    unit: plain per-gate algorithmic bytes per second."""
+    import oracle
+    from circuits import layered_circuit
+    n = 20
+    gates = layered_circuit(n, DEPTH, SEED)
+    import numpy as np
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[0] = 1.0
+    done = 0
+    nbytes = 0
+    t0 = time.perf_counter()
+    for g in gates:
+        t, c, u = oracle.gate_spec(g.name, g.qubits, g.params)
+        psi = oracle.apply_gate(psi, n, u, t, c)
+        diag_masked = g.name in ("cz", "cp")
+        free = n - len(c) - (len(t) if diag_masked else 0)
+        nbytes += 2 * (1 << free) * 16
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"first {done} of {len(gates)} gates of the 20-qubit "
+                       f"instance (depth {DEPTH}, seed {SEED}), complex128, "
+                       f"{dt:.1f} s; bytes counted as plain per-gate passes")}
+
+
+def run_cpu_baseline(budget_s: float) -> dict:
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = "1"
+    r = subprocess.run([sys.executable, os.path.abspath(__file__),
+                        "--cpu-leg", str(budget_s)], env=env,
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return {"value": None, "unit": "GB/s", "cores": 1, "kind": "oracle",
+                "sample": "failed: " + r.stderr[-300:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+# --------------------------------------------------------------- GPU leg
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--strategy", default="tiled",
+                    choices=["plain", "tiled", "fused"])
+    ap.add_argument("--tile-log2", type=int, default=0)
+    ap.add_argument("--low-qubits", type=int, default=0)
+    ap.add_argument("--reg-log2", type=int, default=0)
+    ap.add_argument("--prec", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--cpu-leg", type=float, default=None,
+                    help=argparse.SUPPRESS)
+    a = ap.parse_args()
+
+    if a.cpu_leg is not None:
+        print(json.dumps(cpu_baseline_leg(a.cpu_leg)))
+        return 0
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); "
+              "the state-vector path here is single-GPU by design.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from circuits import layered_circuit
+    from paper_2502_11385_amd import qsv
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    prec = qsv.QSV_C64 if a.prec == "c64" else qsv.QSV_C128
+    b = 8 if prec == qsv.QSV_C64 else 16
+    n = N_QUBITS
+    strat = {"plain": qsv.PLAN_PLAIN, "tiled": qsv.PLAN_TILED,
+             "fused": qsv.PLAN_FUSED}[a.strategy]
+    opts = qsv.fuse_opts(strategy=strat, tile_log2=a.tile_log2,
+                         low_qubits=a.low_qubits, reg_log2=a.reg_log2)
+
+    gates = layered_circuit(n, DEPTH, SEED)
+    circ = qsv.Circuit.from_gates(gates)
+    circ.arrays()
+    stream = torch.cuda.current_stream()
+    state = qsv.State(n, prec, stream=stream)
+    probs = torch.empty(1 << n, dtype=torch.float32, device="cuda")
+    top = list(range(n - 10, n))
+    state.set_profiling(True)
+
+    def step():
+        state.init_basis(0)
+        state.apply_fused(circ, opts)
+        state.probabilities_into(probs.data_ptr(), False)
+        marg = state.marginal(top)            # waits for the stream
+        smp = state.sample(SHOTS, SAMPLE_SEED)  # waits for the stream
+        return marg, smp
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = state.plan_stats()
+
+    pass_ms, pass_kind = [], []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        marg, smp = step()
+        ms, kinds = state.pass_times()
+        pass_ms.append(ms)
+        pass_kind.append(kinds)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    ms_all = np.concatenate(pass_ms)
+    kinds_all = np.concatenate(pass_kind)
+    state_bytes = b << n
+    # algorithmic bytes of one step
+    step_bytes = (state_bytes                      # init (write)
+                  + stats["alg_bytes"]             # gate passes
+                  + state_bytes + (4 << n)         # probabilities
+                  + state_bytes                    # marginal (read)
+                  + state_bytes                    # sampling block sums
+                  + SHOTS * (b << 10))             # per-shot block reread
+    ms_per_step = dt / a.steps * 1e3
+    value = step_bytes * a.steps / dt / 1e9
+
+    # dominant kernel: the tile pass (or the kind with most time)
+    kind_names = {1: "dense/diag (plain)", 2: "tile_kernel", 3: "fused"}
+    tot = {k: float(ms_all[kinds_all == k].sum()) for k in (1, 2, 3)}
+    dom = max(tot, key=tot.get)
+    sel = ms_all[kinds_all == dom]
+    avg_ms = float(sel.mean())
+    per_launch = 2 * state_bytes if dom in (2, 3) else \
+        stats["alg_bytes"] / max(1, stats["passes"])
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    gate_pass_gbps = stats["alg_bytes"] / (float(np.mean(
+        [m.sum() for m in pass_ms])) * 1e-3) / 1e9
+    circuit_ms = float(np.mean([m.sum() for m in pass_ms]))
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE) and dom == 2 and prec == qsv.QSV_C64:
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_sha256_16") == _src_hash(TILE_SRC) and \
+                tr.get("strategy") == a.strategy:
+            traffic = tr.get("bytes_per_launch")
+
+    if a.copy_probe:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == qsv.QSV_C64 else "f64",
+        "data": "synthetic (seeded layered random circuit)",
+        "config": {
+            "workload": (f"layered random circuit, {n} qubits, depth {DEPTH} "
+                         f"(1200 U3 + 580 CZ, seed {SEED}), "
+                         f"{'complex64' if b == 8 else 'complex128'}, "
+                         f"{a.strategy} plan; step = init + gate passes + "
+                         f"probabilities + top-10 marginal + "
+                         f"{SHOTS} samples"),
+            "n_qubits": n, "depth": DEPTH, "gates": len(gates),
+            "strategy": a.strategy, "parallelism": "single GPU",
+        },
+        "depth40_circuit_ms": round(circuit_ms, 3),
+        "gate_pass_GBps": round(gate_pass_gbps, 1),
+        "gate_pass_pct_of_peak": round(100 * gate_pass_gbps / PEAK_HBM_GBPS, 1),
+        "passes": stats["passes"], "tile_segments": stats["segments"],
+        "plan_ms": round(stats["plan_ns"] / 1e6, 3),
+        "top10_marginal_sum": float(np.sum(marg)),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "traffic": traffic,
+                     "kernel": kind_names[dom],
+                     "bytes_per_launch": per_launch,
+                     "avg_launch_ms": round(avg_ms, 4),
+                     "launches": int(sel.size)},
+    }
+    state.free()
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = run_cpu_baseline(a.cpu_budget)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,249 @@
+/*
+ * qsv -- dense quantum state-vector engine for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libqsv.so.  Plain pointers and sizes only.
+ *
+ * The operation every call serves is the evaluation step of both simulation
+ * methods compared in the paper: apply a circuit's gates to a 2^n complex
+ * amplitude vector, then reduce it to the output probability vector
+ * (Section IV.A, Evaluator: the state-vector run followed by the conversion
+ * of the state to probabilities).  Full-circuit execution runs it once on the
+ * whole vector; circuit cutting runs it on every subcircuit variant.
+ *
+ * Conventions shared by all calls
+ * -------------------------------
+ * - State layout: one contiguous device array a[0 .. 2^n - 1] of interleaved
+ *   (re, im) pairs, float for QSV_C64 (8 B per amplitude) and double for
+ *   QSV_C128 (16 B per amplitude); Table III sizes the complex128 case as
+ *   16 * 2^n bytes.
+ * - Index convention: little-endian.  Bit q of an index is the value of
+ *   qubit q.
+ * - Gate matrices: 2^k x 2^k complex, row-major, interleaved (re, im) doubles
+ *   in host memory.  Row/column index r = sum_j bit(q = targets[j]) * 2^j,
+ *   i.e. targets[0] is the least significant bit of r.  A gate with controls
+ *   acts only on amplitudes whose control bits are all 1.
+ * - Errors: every call returns a qsv_status; the library never aborts.
+ *   Argument validation is synchronous, on the host, before any device work,
+ *   and leaves the state unchanged on error.  qsv_last_error() returns a
+ *   thread-local message for the last failing call on the calling thread.
+ * - Device faults surface as QSV_ERR_DEVICE at the next call that
+ *   synchronises; the state is then marked failed and later calls on it
+ *   return QSV_ERR_DEVICE.  Other states are unaffected.
+ * - Ownership: input arrays (qubit lists, matrices, circuits) are copied or
+ *   consumed before the call returns; the caller may free them at once.
+ *   Output buffers belong to the caller.
+ * - Streams: each state is bound to one HIP stream (hipStream_t passed as
+ *   void*, NULL = the default stream).  Apply calls only enqueue work and
+ *   return; calls that return host data (norm, marginal, sample, get) wait
+ *   for the state's stream.  One state must not be used from two threads at
+ *   once; different states are independent.
+ */
+#ifndef QSV_H
+#define QSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QSV_OK = 0,
+  QSV_ERR_INVALID_ARG = 1,   /* bad pointer, qubit, size or option value */
+  QSV_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed */
+  QSV_ERR_DEVICE = 3,        /* a HIP call or kernel failed */
+  QSV_ERR_UNSUPPORTED = 4,   /* unknown precision, gate or strategy */
+  QSV_ERR_BUDGET = 5         /* request larger than an admission budget */
+} qsv_status;
+
+typedef enum { QSV_C64 = 1, QSV_C128 = 2 } qsv_precision;
+
+#define QSV_MAX_QUBITS 34  /* 2^34 c64 amplitudes = 128 GiB fit in 288 GB */
+#define QSV_MAX_TARGETS 5  /* largest k of a dense gate or fused block */
+
+typedef struct qsv_state_s* qsv_state;
+
+/* ---------------------------------------------------------------- states */
+
+/* Allocate a 2^n_qubits state of precision prec on the current HIP device,
+ * bound to hip_stream.  The library owns the 2^n * (8|16) bytes and frees
+ * them in qsv_free.  The contents are undefined until initialised.
+ * 1 <= n_qubits <= QSV_MAX_QUBITS. */
+qsv_status qsv_alloc(int32_t n_qubits, int32_t prec, void* hip_stream,
+                     qsv_state* out);
+
+/* Bind a state to caller-owned device memory (e.g. a torch tensor's
+ * storage) of at least 2^n * (8|16) bytes, 16-byte aligned.  The caller
+ * keeps the memory alive until qsv_free; qsv_free does not release it. */
+qsv_status qsv_wrap(int32_t n_qubits, int32_t prec, void* device_ptr,
+                    size_t bytes, void* hip_stream, qsv_state* out);
+
+/* Release a state (and, for qsv_alloc states, its memory).  NULL is a
+ * no-op.  Waits for the state's pending work first. */
+qsv_status qsv_free(qsv_state s);
+
+/* Set the state to the computational basis state |index>: a[index] = 1,
+ * every other amplitude 0.  index < 2^n.  (Each subcircuit variant starts
+ * from such a state before its cut-input preparation, Section III.A.) */
+qsv_status qsv_init_basis(qsv_state s, uint64_t index);
+
+/* ----------------------------------------------------------------- gates */
+
+/* Apply one gate: the 2^k x 2^k matrix on targets[0..k-1], controlled on
+ * controls[0..c-1] (all must be 1).  1 <= k <= QSV_MAX_TARGETS; targets and
+ * controls are distinct qubits < n.  The update is, for every base index i
+ * with all target bits 0 and all control bits 1,
+ *   a'[i_r] = sum_s U[r][s] a[i_s],  i_r = i | sum_j bit_j(r) << targets[j].
+ * This is the per-gate kernel of full-circuit execution (Section III.B,
+ * gates u1/u3/CNOT of the cache-blocking example).  Enqueued on the state's
+ * stream; the matrix is copied before return. */
+qsv_status qsv_apply_gate(qsv_state s, const int32_t* targets, int32_t k,
+                          const int32_t* controls, int32_t c,
+                          const double* matrix);
+
+/* A gate list, all arrays host-resident, consumed before return.
+ *   k[g], c[g]  : number of targets / controls of gate g
+ *   qubits      : concatenated per gate: k[g] targets then c[g] controls
+ *   matrices    : concatenated per gate: 2^k[g] x 2^k[g] complex matrices
+ *                 (interleaved re/im doubles, row-major) */
+typedef struct {
+  size_t n_gates;
+  const int32_t* k;
+  const int32_t* c;
+  const int32_t* qubits;
+  const double* matrices;
+} qsv_circuit;
+
+typedef enum {
+  QSV_PLAN_AUTO = 0,   /* tiled runs, plain kernels where a tile cannot go */
+  QSV_PLAN_PLAIN = 1,  /* one kernel per gate */
+  QSV_PLAN_TILED = 2,  /* LDS-staged tiles applying runs of gates per pass */
+  QSV_PLAN_FUSED = 3   /* fused k-qubit unitaries (built in FP64 on device) */
+} qsv_strategy;
+
+/* Options of qsv_apply_fused; all-zero (or NULL) selects defaults.
+ *   tile_log2  : tile size L (amplitudes per tile = 2^L), 10..13
+ *                (default 12 for c64, 11 for c128)
+ *   k_max      : widest fused block, 1..5 (default 5)
+ *   low_qubits : qubits 0..low_qubits-1 belong to every tile so that HBM
+ *                accesses are contiguous runs (default 5 c64, 4 c128)
+ *   reg_log2   : amplitudes per thread inside a tile, as log2 (4 or 5;
+ *                default 4)
+ * This is the single-GPU form of the chunking and cache blocking of
+ * Section III.B: a tile of 2^L amplitudes plays the role of a 2^nc chunk
+ * (blocking_qubits), and the planner reorders commuting gates so that runs
+ * of gates touch only the tile's qubits. */
+typedef struct {
+  int32_t strategy;
+  int32_t tile_log2;
+  int32_t k_max;
+  int32_t low_qubits;
+  int32_t reg_log2;
+} qsv_fuse_opts;
+
+/* Plan and apply a whole gate list.  The result equals applying the gates
+ * one by one in list order (up to rounding): passes only regroup gates that
+ * commute (disjoint qubits, or both diagonal).  Enqueued on the state's
+ * stream. */
+qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
+                           const qsv_fuse_opts* opts);
+
+/* Statistics of the last qsv_apply_fused on this state:
+ *   out[0] passes launched, out[1] gates, out[2] algorithmic HBM bytes
+ *   (sum over passes of bytes read + written), out[3] tile passes,
+ *   out[4] plain passes, out[5] fused passes, out[6] tile segments,
+ *   out[7] host planning time in nanoseconds.  n_out <= 8 entries. */
+qsv_status qsv_last_plan_stats(qsv_state s, uint64_t* out, int32_t n_out);
+
+/* Per-pass timing.  While enabled (enable != 0), qsv_apply_fused records
+ * a HIP event pair around every pass it launches, on the state's stream.
+ * qsv_pass_times waits for the last qsv_apply_fused to finish and writes,
+ * for its first min(cap, passes) passes, the kernel time in milliseconds
+ * (ms_out) and the pass kind (kinds_out: 1 plain, 2 tile, 3 fused; may be
+ * NULL); *count receives the number of passes recorded. */
+qsv_status qsv_set_profiling(qsv_state s, int32_t enable);
+qsv_status qsv_pass_times(qsv_state s, float* ms_out, int32_t* kinds_out,
+                          int32_t cap, int32_t* count);
+
+/* Host-only planner dry run (no device work; usable without a GPU).
+ * For n_qubits and precision prec, writes for each gate g:
+ *   gate_pass[g]  : index of the pass that applies g
+ *   gate_order[j] : the j-th gate applied (a permutation of 0..n_gates-1)
+ * and for each pass p (< *n_passes, at most n_gates):
+ *   pass_kind[p]  : 1 plain, 2 tile, 3 fused
+ *   pass_qubits[p]: bit mask of the pass's qubit set (tile: its 2^L qubit
+ *                   set; fused: the block's qubits; plain: the gate's) */
+qsv_status qsv_plan_describe(const qsv_circuit* circ, int32_t n_qubits,
+                             int32_t prec, const qsv_fuse_opts* opts,
+                             int32_t* gate_pass, int32_t* gate_order,
+                             int32_t* pass_kind, uint64_t* pass_qubits,
+                             int32_t* n_passes);
+
+/* Standard gate matrix by name into out (2^k x 2^k complex, interleaved),
+ * with *k_out its target count.  Names: "h","x","y","z","s","sdg","p"(1),
+ * "u3"(3: theta, phi, lambda; the OpenQASM 2 U3, used as u3 in the
+ * cache-blocking example of Section III.B), "id".  out holds >= 8 doubles. */
+qsv_status qsv_gate_matrix(const char* name, const double* params,
+                           int32_t n_params, double* out, int32_t* k_out);
+
+/* ------------------------------------------------------------ reductions */
+
+/* p_i = |a_i|^2 for all 2^n amplitudes into out_dev (caller-owned device
+ * memory), as double if out_fp64 != 0 else float.  c64 states compute p in
+ * FP64 from the FP32 amplitudes before rounding.  (The probability vector
+ * the evaluator returns, Section IV.A.)  Enqueued on the state's stream. */
+qsv_status qsv_probabilities(qsv_state s, void* out_dev, int32_t out_fp64);
+
+/* Sum of p_i in FP64 with Neumaier compensation in a fixed-order tree
+ * (bitwise reproducible for a given state).  Waits for the stream. */
+qsv_status qsv_norm(qsv_state s, double* out);
+
+/* Divide every amplitude by sqrt(norm); returns the norm before scaling in
+ * *norm_out (may be NULL).  Waits for the stream. */
+qsv_status qsv_renormalize(qsv_state s, double* norm_out);
+
+/* Marginal distribution of the specified qubits (the Builder's
+ * distribution of specified qubits, Section IV.A):
+ *   out[j] = sum of p_i over i with bit qubits[l] of i == bit l of j,
+ * qubits[0] the least significant bit of j; 1 <= m <= 20, distinct qubits.
+ * out_host holds 2^m doubles.  FP64 with Neumaier compensation in a fixed
+ * order.  Waits for the stream. */
+qsv_status qsv_marginal(qsv_state s, const int32_t* qubits, int32_t m,
+                        double* out_host);
+
+/* n_shots basis indices drawn from p (shots, Section III.A).  Draw j uses
+ * u_j = (SplitMix64(seed, j) >> 11) * 2^-53, SplitMix64(seed, j) being
+ * output j of the SplitMix64 generator (Steele, Lea & Flood 2014) seeded
+ * with seed, and returns the least i with C(i) > u_j * C(2^n - 1), C the
+ * inclusive FP64 cumulative sum of p (accumulated per 1024-amplitude block,
+ * then within the block).  out_host receives n_shots indices in draw
+ * order.  n_shots <= 2^32.  Waits for the stream. */
+qsv_status qsv_sample(qsv_state s, uint64_t n_shots, uint64_t seed,
+                      uint64_t* out_host);
+
+/* ---------------------------------------------------- copies and control */
+
+/* Copy all amplitudes to / from host memory (2^n interleaved pairs of the
+ * state's precision).  Used for tests and checkpoints.  Waits. */
+qsv_status qsv_get_amplitudes(qsv_state s, void* host_out);
+qsv_status qsv_set_amplitudes(qsv_state s, const void* host_in);
+
+/* Device pointer, qubit count and precision of a state. */
+qsv_status qsv_info(qsv_state s, void** device_ptr, int32_t* n_qubits,
+                    int32_t* prec);
+
+/* Wait for the state's stream; reports deferred device errors. */
+qsv_status qsv_sync(qsv_state s);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* qsv_last_error(void);
+
+/* Library version string. */
+const char* qsv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSV_H */

@@ -1,0 +1,803 @@
+// C ABI of libqsv: state lifecycle, argument validation, program upload and
+// pass dispatch.  Every argument check runs on the host before any device
+// call, so a rejected call leaves the state untouched.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device_common.h"
+#include "planner.h"
+#include "program.h"
+#include "qsv.h"
+
+using namespace qsv;
+
+struct qsv_state_s {
+  int n = 0;
+  int prec = 0;
+  int b = 0;  // bytes per amplitude
+  void* amp = nullptr;
+  bool owned = false;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool failed = false;
+  // program buffer (device) and its pinned host staging copy
+  char* prog_dev = nullptr;
+  size_t prog_cap = 0;
+  char* prog_host = nullptr;
+  size_t host_cap = 0;
+  hipEvent_t upload_done = nullptr;
+  bool upload_pending = false;
+  // reduction scratch
+  char* scratch = nullptr;
+  size_t scratch_cap = 0;
+  uint64_t stats[8] = {0};
+  // per-pass timing
+  bool profiling = false;
+  std::vector<hipEvent_t> evs;
+  std::vector<int32_t> ev_kinds;
+  int32_t ev_used = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+qsv_status fail(qsv_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+qsv_status device_fail(qsv_state s, hipError_t e, const char* what) {
+  if (s) s->failed = true;
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? QSV_ERR_OUT_OF_MEMORY : QSV_ERR_DEVICE;
+}
+
+#define QSV_HIP(s, call)                                 \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return device_fail(s, e_, #call); \
+  } while (0)
+
+qsv_status check_state(qsv_state s) {
+  if (!s) return fail(QSV_ERR_INVALID_ARG, "null state");
+  if (s->failed)
+    return fail(QSV_ERR_DEVICE, "state is in a failed state after a device error");
+  return QSV_OK;
+}
+
+qsv_status select_device(qsv_state s) {
+  int cur = -1;
+  QSV_HIP(s, hipGetDevice(&cur));
+  if (cur != s->device) QSV_HIP(s, hipSetDevice(s->device));
+  return QSV_OK;
+}
+
+int bytes_of(int prec) { return prec == QSV_C64 ? 8 : 16; }
+
+qsv_status ensure_scratch(qsv_state s, size_t bytes) {
+  if (bytes <= s->scratch_cap) return QSV_OK;
+  QSV_HIP(s, hipStreamSynchronize(s->stream));
+  if (s->scratch) QSV_HIP(s, hipFree(s->scratch));
+  s->scratch = nullptr;
+  s->scratch_cap = 0;
+  size_t cap = std::max(bytes, size_t(1) << 16);
+  hipError_t e = hipMalloc(&s->scratch, cap);
+  if (e != hipSuccess) {
+    s->scratch = nullptr;
+    (void)hipGetLastError();
+    return fail(QSV_ERR_OUT_OF_MEMORY, "scratch allocation failed");
+  }
+  s->scratch_cap = cap;
+  return QSV_OK;
+}
+
+// Copy `bytes` of host data into the state's device program buffer, in
+// stream order (kernels already enqueued keep reading the previous
+// program until the copy runs).
+qsv_status upload(qsv_state s, const void* data, size_t bytes) {
+  if (bytes == 0) return QSV_OK;
+  if (bytes > s->prog_cap) {
+    const size_t old = s->prog_cap;
+    QSV_HIP(s, hipStreamSynchronize(s->stream));
+    if (s->prog_dev) QSV_HIP(s, hipFree(s->prog_dev));
+    s->prog_dev = nullptr;
+    s->prog_cap = 0;
+    size_t cap = std::max(bytes, std::max(size_t(1) << 16, 2 * old));
+    hipError_t e = hipMalloc(&s->prog_dev, cap);
+    if (e != hipSuccess) {
+      s->prog_dev = nullptr;
+      (void)hipGetLastError();
+      return fail(QSV_ERR_OUT_OF_MEMORY, "program buffer allocation failed");
+    }
+    s->prog_cap = cap;
+  }
+  if (s->upload_pending) {
+    QSV_HIP(s, hipEventSynchronize(s->upload_done));
+    s->upload_pending = false;
+  }
+  if (bytes > s->host_cap) {
+    if (s->prog_host) QSV_HIP(s, hipHostFree(s->prog_host));
+    s->prog_host = nullptr;
+    s->host_cap = 0;
+    size_t cap = std::max(bytes, size_t(1) << 16);
+    hipError_t e = hipHostMalloc(&s->prog_host, cap, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      s->prog_host = nullptr;
+      (void)hipGetLastError();
+      return fail(QSV_ERR_OUT_OF_MEMORY, "pinned staging allocation failed");
+    }
+    s->host_cap = cap;
+  }
+  std::memcpy(s->prog_host, data, bytes);
+  QSV_HIP(s, hipMemcpyAsync(s->prog_dev, s->prog_host, bytes,
+                            hipMemcpyHostToDevice, s->stream));
+  QSV_HIP(s, hipEventRecord(s->upload_done, s->stream));
+  s->upload_pending = true;
+  return QSV_OK;
+}
+
+qsv_status parse_circuit(const qsv_circuit* circ, int n,
+                         std::vector<HostGate>* out) {
+  if (!circ) return fail(QSV_ERR_INVALID_ARG, "null circuit");
+  out->clear();
+  if (circ->n_gates == 0) return QSV_OK;
+  if (!circ->k || !circ->c || !circ->qubits || !circ->matrices)
+    return fail(QSV_ERR_INVALID_ARG, "null circuit array");
+  out->resize(circ->n_gates);
+  size_t qo = 0, mo = 0;
+  for (size_t i = 0; i < circ->n_gates; ++i) {
+    const int k = circ->k[i], c = circ->c[i];
+    std::string err = make_gate(n, k, c, circ->qubits + qo,
+                                circ->matrices + mo, &(*out)[i]);
+    if (!err.empty())
+      return fail(QSV_ERR_INVALID_ARG, "gate " + std::to_string(i) + ": " + err);
+    qo += size_t(k + c);
+    mo += size_t(2) << (2 * k);
+  }
+  return QSV_OK;
+}
+
+template <class T>
+size_t put(std::vector<char>& buf, const T* data, size_t count) {
+  size_t off = (buf.size() + 255) & ~size_t(255);
+  buf.resize(off + sizeof(T) * count);
+  if (count) std::memcpy(buf.data() + off, data, sizeof(T) * count);
+  return off;
+}
+
+}  // namespace
+
+// ======================================================================
+
+extern "C" {
+
+const char* qsv_last_error(void) { return g_err.c_str(); }
+
+const char* qsv_version(void) { return "qsv 0.1 (gfx950)"; }
+
+qsv_status qsv_alloc(int32_t n, int32_t prec, void* stream, qsv_state* out) {
+  if (!out) return fail(QSV_ERR_INVALID_ARG, "null output pointer");
+  *out = nullptr;
+  if (prec != QSV_C64 && prec != QSV_C128)
+    return fail(QSV_ERR_UNSUPPORTED, "unknown precision");
+  if (n < 1 || n > QSV_MAX_QUBITS)
+    return fail(QSV_ERR_INVALID_ARG, "n_qubits must be 1..34");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(nullptr, e, "hipGetDevice");
+  const size_t bytes = size_t(bytes_of(prec)) << n;
+  void* p = nullptr;
+  e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(QSV_ERR_OUT_OF_MEMORY,
+                "state allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  qsv_state s = new qsv_state_s;
+  s->n = n;
+  s->prec = prec;
+  s->b = bytes_of(prec);
+  s->amp = p;
+  s->owned = true;
+  s->stream = static_cast<hipStream_t>(stream);
+  s->device = dev;
+  e = hipEventCreateWithFlags(&s->upload_done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    delete s;
+    return device_fail(nullptr, e, "hipEventCreate");
+  }
+  *out = s;
+  return QSV_OK;
+}
+
+qsv_status qsv_wrap(int32_t n, int32_t prec, void* ptr, size_t bytes,
+                    void* stream, qsv_state* out) {
+  if (!out) return fail(QSV_ERR_INVALID_ARG, "null output pointer");
+  *out = nullptr;
+  if (prec != QSV_C64 && prec != QSV_C128)
+    return fail(QSV_ERR_UNSUPPORTED, "unknown precision");
+  if (n < 1 || n > QSV_MAX_QUBITS)
+    return fail(QSV_ERR_INVALID_ARG, "n_qubits must be 1..34");
+  if (!ptr) return fail(QSV_ERR_INVALID_ARG, "null device pointer");
+  if (reinterpret_cast<uintptr_t>(ptr) % 16)
+    return fail(QSV_ERR_INVALID_ARG, "device pointer not 16-byte aligned");
+  if (bytes < (size_t(bytes_of(prec)) << n))
+    return fail(QSV_ERR_INVALID_ARG, "buffer smaller than 2^n amplitudes");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(nullptr, e, "hipGetDevice");
+  qsv_state s = new qsv_state_s;
+  s->n = n;
+  s->prec = prec;
+  s->b = bytes_of(prec);
+  s->amp = ptr;
+  s->owned = false;
+  s->stream = static_cast<hipStream_t>(stream);
+  s->device = dev;
+  e = hipEventCreateWithFlags(&s->upload_done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete s;
+    return device_fail(nullptr, e, "hipEventCreate");
+  }
+  *out = s;
+  return QSV_OK;
+}
+
+qsv_status qsv_free(qsv_state s) {
+  if (!s) return QSV_OK;
+  (void)select_device(s);
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (s->owned && s->amp) (void)hipFree(s->amp);
+  if (s->prog_dev) (void)hipFree(s->prog_dev);
+  if (s->scratch) (void)hipFree(s->scratch);
+  if (s->prog_host) (void)hipHostFree(s->prog_host);
+  if (s->upload_done) (void)hipEventDestroy(s->upload_done);
+  for (hipEvent_t e2 : s->evs) (void)hipEventDestroy(e2);
+  delete s;
+  if (e != hipSuccess) return device_fail(nullptr, e, "hipStreamSynchronize");
+  return QSV_OK;
+}
+
+qsv_status qsv_info(qsv_state s, void** ptr, int32_t* n, int32_t* prec) {
+  if (!s) return fail(QSV_ERR_INVALID_ARG, "null state");
+  if (ptr) *ptr = s->amp;
+  if (n) *n = s->n;
+  if (prec) *prec = s->prec;
+  return QSV_OK;
+}
+
+qsv_status qsv_sync(qsv_state s) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if ((st = select_device(s)) != QSV_OK) return st;
+  QSV_HIP(s, hipStreamSynchronize(s->stream));
+  return QSV_OK;
+}
+
+qsv_status qsv_init_basis(qsv_state s, uint64_t index) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if (index >= (uint64_t(1) << s->n))
+    return fail(QSV_ERR_INVALID_ARG, "basis index >= 2^n");
+  if ((st = select_device(s)) != QSV_OK) return st;
+  QSV_HIP(s, launch_fill_basis(s->prec, s->amp, s->n, index, s->stream));
+  return QSV_OK;
+}
+
+qsv_status qsv_apply_gate(qsv_state s, const int32_t* targets, int32_t k,
+                          const int32_t* controls, int32_t c,
+                          const double* matrix) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if (k < 1 || k > QSV_MAX_TARGETS)
+    return fail(QSV_ERR_INVALID_ARG, "k must be 1..5");
+  if (!targets) return fail(QSV_ERR_INVALID_ARG, "null targets");
+  if (c < 0) return fail(QSV_ERR_INVALID_ARG, "negative control count");
+  if (c > 0 && !controls) return fail(QSV_ERR_INVALID_ARG, "null controls");
+  if (k + c > s->n)
+    return fail(QSV_ERR_INVALID_ARG, "too many targets + controls for n");
+  std::vector<int32_t> qs(targets, targets + k);
+  if (c > 0) qs.insert(qs.end(), controls, controls + c);
+  HostGate g;
+  std::string err = make_gate(s->n, k, c, qs.data(), matrix, &g);
+  if (!err.empty()) return fail(QSV_ERR_INVALID_ARG, err);
+  if ((st = select_device(s)) != QSV_OK) return st;
+  if (g.diagonal) {
+    QSV_HIP(s, launch_diag(s->prec, s->amp, s->n, g, s->stream));
+  } else if (g.k <= 2) {
+    QSV_HIP(s, launch_dense(s->prec, s->amp, s->n, g, nullptr, s->stream));
+  } else {
+    if ((st = upload(s, g.m.data(), g.m.size() * sizeof(double))) != QSV_OK)
+      return st;
+    QSV_HIP(s, launch_dense(s->prec, s->amp, s->n, g,
+                            reinterpret_cast<const double*>(s->prog_dev),
+                            s->stream));
+  }
+  return QSV_OK;
+}
+
+static qsv_status plan_for(const qsv_circuit* circ, int n, int prec,
+                           const qsv_fuse_opts* opts,
+                           std::vector<HostGate>* G, PlanOptions* po,
+                           Plan* plan) {
+  qsv_status st = parse_circuit(circ, n, G);
+  if (st != QSV_OK) return st;
+  int v[5] = {0, 0, 0, 0, 0};
+  if (opts) {
+    v[0] = opts->strategy;
+    v[1] = opts->tile_log2;
+    v[2] = opts->k_max;
+    v[3] = opts->low_qubits;
+    v[4] = opts->reg_log2;
+  }
+  std::string err = resolve_options(n, bytes_of(prec), v, po);
+  if (!err.empty())
+    return fail(v[0] < 0 || v[0] > 3 ? QSV_ERR_UNSUPPORTED : QSV_ERR_INVALID_ARG,
+                err);
+  make_plan(*G, n, bytes_of(prec), *po, plan);
+  return QSV_OK;
+}
+
+qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
+                           const qsv_fuse_opts* opts) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<HostGate> G;
+  PlanOptions po;
+  Plan plan;
+  if ((st = plan_for(circ, s->n, s->prec, opts, &G, &po, &plan)) != QSV_OK)
+    return st;
+  const int n = s->n;
+
+  // ---- serialise the program
+  std::vector<TilePass> tpasses;
+  std::vector<TileSeg> tsegs;
+  std::vector<TileOp> tops;
+  std::vector<FusedBlock> fblocks;
+  std::vector<FusedGate> fgates;
+  std::vector<double> mats;             // gate matrices (FP64)
+  std::vector<int64_t> plain_moff(plan.passes.size(), -1);
+  size_t u64_total = 0, u32_total = 0;  // fused outputs (in doubles/floats)
+
+  for (size_t pi = 0; pi < plan.passes.size(); ++pi) {
+    const Pass& p = plan.passes[pi];
+    if (p.kind == kPassTile) {
+      TilePass tp = {};
+      tp.L = p.L;
+      tp.nseg = int32_t(p.segs.size());
+      tp.seg_begin = int32_t(tsegs.size());
+      int local_of[64];
+      for (int j = 0; j < p.L; ++j) {
+        tp.q[j] = p.q[j];
+        local_of[p.q[j]] = j;
+      }
+      for (const auto& sg : p.segs) {
+        TileSeg ts = {};
+        for (int i = 0; i < po.reg_log2; ++i) ts.reg_bits[i] = sg.reg_bits[i];
+        ts.op_begin = int32_t(tops.size());
+        for (int gi : sg.gates) {
+          const HostGate& g = G[gi];
+          TileOp op = {};
+          for (int j = 0; j < g.c; ++j) {
+            const int q = g.ctl[j];
+            if (p.qubits >> q & 1)
+              op.lctrl |= 1u << local_of[q];
+            else
+              op.gctrl |= uint64_t(1) << q;
+          }
+          const int d = 1 << g.k;
+          if (!g.diagonal) {
+            op.kind = kOpDense1;
+            const int lb = local_of[g.t[0]];
+            op.reg = -1;
+            for (int i = 0; i < po.reg_log2; ++i)
+              if (sg.reg_bits[i] == lb) op.reg = i;
+            if (op.reg < 0)
+              return fail(QSV_ERR_DEVICE, "internal planner error: target "
+                                          "not in a register bit");
+            for (int e = 0; e < 8; ++e) op.m[e] = g.m[e];
+          } else if (g.masked_phase) {
+            op.kind = kOpPhase;
+            for (int j = 0; j < g.k; ++j) {
+              const int q = g.t[j];
+              if (p.qubits >> q & 1)
+                op.lctrl |= 1u << local_of[q];
+              else
+                op.gctrl |= uint64_t(1) << q;
+            }
+            op.m[0] = g.m[2 * ((d - 1) * d + (d - 1))];
+            op.m[1] = g.m[2 * ((d - 1) * d + (d - 1)) + 1];
+          } else {
+            op.kind = kOpDiag;
+            op.dk = g.k;
+            int* db[2] = {&op.dbit0, &op.dbit1};
+            for (int j = 0; j < g.k; ++j) {
+              const int q = g.t[j];
+              *db[j] = (p.qubits >> q & 1) ? local_of[q] : -1 - q;
+            }
+            for (int r = 0; r < d; ++r) {
+              op.m[2 * r] = g.m[2 * (r * d + r)];
+              op.m[2 * r + 1] = g.m[2 * (r * d + r) + 1];
+            }
+          }
+          tops.push_back(op);
+        }
+        ts.op_end = int32_t(tops.size());
+        tsegs.push_back(ts);
+      }
+      tpasses.push_back(tp);
+    } else if (p.kind == kPassPlain) {
+      const HostGate& g = G[p.gates[0]];
+      if (!g.diagonal && g.k >= 3) {
+        plain_moff[pi] = int64_t(mats.size());
+        mats.insert(mats.end(), g.m.begin(), g.m.end());
+      }
+    } else {
+      FusedBlock fb = {};
+      fb.k = p.fk;
+      fb.n_gates = int32_t(p.gates.size());
+      fb.gate_begin = int32_t(fgates.size());
+      int local_of[64];
+      for (int j = 0; j < p.fk; ++j) {
+        fb.q[j] = p.fq[j];
+        local_of[p.fq[j]] = j;
+      }
+      for (int gi : p.gates) {
+        const HostGate& g = G[gi];
+        FusedGate fg = {};
+        fg.k = g.k;
+        fg.c = g.c;
+        for (int j = 0; j < g.k; ++j) fg.t[j] = local_of[g.t[j]];
+        for (int j = 0; j < g.c; ++j) fg.ctl[j] = local_of[g.ctl[j]];
+        fg.m_offset = int64_t(mats.size());
+        mats.insert(mats.end(), g.m.begin(), g.m.end());
+        fgates.push_back(fg);
+      }
+      const size_t dd = size_t(2) << (2 * p.fk);
+      fb.u64_offset = int64_t(u64_total);
+      fb.u32_offset = int64_t(u32_total);
+      u64_total += dd;
+      u32_total += dd;
+      fblocks.push_back(fb);
+    }
+  }
+  // Fused outputs follow the gate matrices in the FP64 region.
+  const size_t gate_doubles = mats.size();
+  for (auto& fb : fblocks) fb.u64_offset += int64_t(gate_doubles);
+  mats.resize(gate_doubles + u64_total, 0.0);
+  std::vector<float> mats32(u32_total, 0.0f);
+
+  std::vector<char> buf;
+  const size_t o_tp = put(buf, tpasses.data(), tpasses.size());
+  const size_t o_ts = put(buf, tsegs.data(), tsegs.size());
+  const size_t o_to = put(buf, tops.data(), tops.size());
+  const size_t o_fb = put(buf, fblocks.data(), fblocks.size());
+  const size_t o_fg = put(buf, fgates.data(), fgates.size());
+  const size_t o_m64 = put(buf, mats.data(), mats.size());
+  const size_t o_m32 = put(buf, mats32.data(), mats32.size());
+  const auto t1 = std::chrono::steady_clock::now();
+
+  if ((st = select_device(s)) != QSV_OK) return st;
+  if ((st = upload(s, buf.data(), buf.size())) != QSV_OK) return st;
+  char* dev = s->prog_dev;
+  const TilePass* d_tp = reinterpret_cast<const TilePass*>(dev + o_tp);
+  const TileSeg* d_ts = reinterpret_cast<const TileSeg*>(dev + o_ts);
+  const TileOp* d_to = reinterpret_cast<const TileOp*>(dev + o_to);
+  double* d_m64 = reinterpret_cast<double*>(dev + o_m64);
+  float* d_m32 = reinterpret_cast<float*>(dev + o_m32);
+
+  if (!fblocks.empty())
+    QSV_HIP(s, launch_fused_build(
+                   reinterpret_cast<const FusedBlock*>(dev + o_fb),
+                   int(fblocks.size()),
+                   reinterpret_cast<const FusedGate*>(dev + o_fg), d_m64,
+                   d_m32, s->stream));
+
+  if (s->profiling) {
+    const size_t need = 2 * plan.passes.size();
+    while (s->evs.size() < need) {
+      hipEvent_t e2;
+      QSV_HIP(s, hipEventCreate(&e2));
+      s->evs.push_back(e2);
+    }
+    s->ev_kinds.assign(plan.passes.size(), 0);
+    s->ev_used = int32_t(plan.passes.size());
+  } else {
+    s->ev_used = 0;
+  }
+  size_t ti = 0, fi = 0;
+  for (size_t pi = 0; pi < plan.passes.size(); ++pi) {
+    const Pass& p = plan.passes[pi];
+    if (s->profiling) {
+      s->ev_kinds[pi] = p.kind;
+      QSV_HIP(s, hipEventRecord(s->evs[2 * pi], s->stream));
+    }
+    if (p.kind == kPassTile) {
+      QSV_HIP(s, launch_tile(s->prec, po.reg_log2, s->amp, n, p.L,
+                             d_tp + ti, d_ts, d_to, s->stream));
+      ++ti;
+    } else if (p.kind == kPassPlain) {
+      const HostGate& g = G[p.gates[0]];
+      if (g.diagonal)
+        QSV_HIP(s, launch_diag(s->prec, s->amp, n, g, s->stream));
+      else
+        QSV_HIP(s, launch_dense(s->prec, s->amp, n, g,
+                                plain_moff[pi] >= 0 ? d_m64 + plain_moff[pi]
+                                                    : nullptr,
+                                s->stream));
+    } else {
+      const FusedBlock& fb = fblocks[fi++];
+      const void* u = (s->prec == QSV_C64 && fb.k >= 4)
+                          ? static_cast<const void*>(d_m32 + fb.u32_offset)
+                          : static_cast<const void*>(d_m64 + fb.u64_offset);
+      QSV_HIP(s, launch_fused_apply(s->prec, s->amp, n, fb.k, fb.q, u,
+                                    s->stream));
+    }
+    if (s->profiling)
+      QSV_HIP(s, hipEventRecord(s->evs[2 * pi + 1], s->stream));
+  }
+  s->stats[0] = plan.passes.size();
+  s->stats[1] = G.size();
+  s->stats[2] = plan.alg_bytes;
+  s->stats[3] = uint64_t(plan.tile_passes);
+  s->stats[4] = uint64_t(plan.plain_passes);
+  s->stats[5] = uint64_t(plan.fused_passes);
+  s->stats[6] = uint64_t(plan.segments);
+  s->stats[7] = uint64_t(
+      std::chrono::duration_cast<std::chrono::nanoseconds>(t1 - t0).count());
+  return QSV_OK;
+}
+
+qsv_status qsv_set_profiling(qsv_state s, int32_t enable) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  s->profiling = enable != 0;
+  return QSV_OK;
+}
+
+qsv_status qsv_pass_times(qsv_state s, float* ms_out, int32_t* kinds_out,
+                          int32_t cap, int32_t* count) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if (!count || cap < 0 || (cap > 0 && !ms_out))
+    return fail(QSV_ERR_INVALID_ARG, "bad output arguments");
+  if ((st = select_device(s)) != QSV_OK) return st;
+  const int32_t m = std::min(cap, s->ev_used);
+  if (s->ev_used > 0)
+    QSV_HIP(s, hipEventSynchronize(s->evs[2 * (s->ev_used - 1) + 1]));
+  for (int32_t i = 0; i < m; ++i) {
+    float ms = 0;
+    QSV_HIP(s, hipEventElapsedTime(&ms, s->evs[2 * i], s->evs[2 * i + 1]));
+    ms_out[i] = ms;
+    if (kinds_out) kinds_out[i] = s->ev_kinds[i];
+  }
+  *count = s->ev_used;
+  return QSV_OK;
+}
+
+qsv_status qsv_last_plan_stats(qsv_state s, uint64_t* out, int32_t n_out) {
+  if (!s) return fail(QSV_ERR_INVALID_ARG, "null state");
+  if (!out || n_out < 0 || n_out > 8)
+    return fail(QSV_ERR_INVALID_ARG, "bad stats buffer");
+  for (int i = 0; i < n_out; ++i) out[i] = s->stats[i];
+  return QSV_OK;
+}
+
+qsv_status qsv_plan_describe(const qsv_circuit* circ, int32_t n, int32_t prec,
+                             const qsv_fuse_opts* opts, int32_t* gate_pass,
+                             int32_t* gate_order, int32_t* pass_kind,
+                             uint64_t* pass_qubits, int32_t* n_passes) {
+  if (prec != QSV_C64 && prec != QSV_C128)
+    return fail(QSV_ERR_UNSUPPORTED, "unknown precision");
+  if (n < 1 || n > QSV_MAX_QUBITS)
+    return fail(QSV_ERR_INVALID_ARG, "n_qubits must be 1..34");
+  if (!n_passes) return fail(QSV_ERR_INVALID_ARG, "null n_passes");
+  std::vector<HostGate> G;
+  PlanOptions po;
+  Plan plan;
+  qsv_status st = plan_for(circ, n, prec, opts, &G, &po, &plan);
+  if (st != QSV_OK) return st;
+  if (!G.empty() && (!gate_pass || !gate_order || !pass_kind || !pass_qubits))
+    return fail(QSV_ERR_INVALID_ARG, "null output array");
+  size_t j = 0;
+  for (size_t pi = 0; pi < plan.passes.size(); ++pi) {
+    const Pass& p = plan.passes[pi];
+    pass_kind[pi] = p.kind;
+    pass_qubits[pi] = p.qubits;
+    for (int gi : p.gates) {
+      gate_pass[gi] = int32_t(pi);
+      gate_order[j++] = gi;
+    }
+  }
+  *n_passes = int32_t(plan.passes.size());
+  return QSV_OK;
+}
+
+qsv_status qsv_gate_matrix(const char* name, const double* params,
+                           int32_t n_params, double* out, int32_t* k_out) {
+  if (!name || !out || !k_out)
+    return fail(QSV_ERR_INVALID_ARG, "null argument");
+  const std::string nm(name);
+  auto need = [&](int cnt) -> bool { return n_params >= cnt && (cnt == 0 || params); };
+  double m[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+  const double r2 = std::sqrt(0.5);
+  if (nm == "id") {
+  } else if (nm == "h") {
+    double v[8] = {r2, 0, r2, 0, r2, 0, -r2, 0};
+    std::memcpy(m, v, sizeof m);
+  } else if (nm == "x") {
+    double v[8] = {0, 0, 1, 0, 1, 0, 0, 0};
+    std::memcpy(m, v, sizeof m);
+  } else if (nm == "y") {
+    double v[8] = {0, 0, 0, -1, 0, 1, 0, 0};
+    std::memcpy(m, v, sizeof m);
+  } else if (nm == "z") {
+    m[6] = -1;
+  } else if (nm == "s") {
+    m[6] = 0;
+    m[7] = 1;
+  } else if (nm == "sdg") {
+    m[6] = 0;
+    m[7] = -1;
+  } else if (nm == "p") {
+    if (!need(1)) return fail(QSV_ERR_INVALID_ARG, "p needs 1 parameter");
+    m[6] = std::cos(params[0]);
+    m[7] = std::sin(params[0]);
+  } else if (nm == "u3") {
+    if (!need(3)) return fail(QSV_ERR_INVALID_ARG, "u3 needs 3 parameters");
+    const double th = params[0], ph = params[1], la = params[2];
+    const double c = std::cos(th / 2), sn = std::sin(th / 2);
+    // [[c, -e^{i la} s], [e^{i ph} s, e^{i (ph + la)} c]]
+    m[0] = c;
+    m[1] = 0;
+    m[2] = -std::cos(la) * sn;
+    m[3] = -std::sin(la) * sn;
+    m[4] = std::cos(ph) * sn;
+    m[5] = std::sin(ph) * sn;
+    m[6] = std::cos(ph + la) * c;
+    m[7] = std::sin(ph + la) * c;
+  } else {
+    return fail(QSV_ERR_UNSUPPORTED, "unknown gate name " + nm);
+  }
+  std::memcpy(out, m, sizeof m);
+  *k_out = 1;
+  return QSV_OK;
+}
+
+qsv_status qsv_probabilities(qsv_state s, void* out_dev, int32_t out_fp64) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if (!out_dev) return fail(QSV_ERR_INVALID_ARG, "null output buffer");
+  if ((st = select_device(s)) != QSV_OK) return st;
+  if ((st = ensure_scratch(s, norm_scratch_bytes(s->n))) != QSV_OK) return st;
+  QSV_HIP(s, launch_probs(s->prec, s->amp, s->n, out_dev, out_fp64 != 0,
+                          reinterpret_cast<double*>(s->scratch), nullptr,
+                          s->stream));
+  return QSV_OK;
+}
+
+static qsv_status norm_dev(qsv_state s, double** where) {
+  const size_t part = norm_scratch_bytes(s->n);
+  qsv_status st = ensure_scratch(s, part + 256);
+  if (st != QSV_OK) return st;
+  double* nd = reinterpret_cast<double*>(s->scratch + ((part + 255) & ~size_t(255)));
+  QSV_HIP(s, launch_probs(s->prec, s->amp, s->n, nullptr, 1,
+                          reinterpret_cast<double*>(s->scratch), nd,
+                          s->stream));
+  *where = nd;
+  return QSV_OK;
+}
+
+qsv_status qsv_norm(qsv_state s, double* out) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if (!out) return fail(QSV_ERR_INVALID_ARG, "null output");
+  if ((st = select_device(s)) != QSV_OK) return st;
+  double* nd = nullptr;
+  if ((st = norm_dev(s, &nd)) != QSV_OK) return st;
+  QSV_HIP(s, hipMemcpyAsync(out, nd, sizeof(double), hipMemcpyDeviceToHost,
+                            s->stream));
+  QSV_HIP(s, hipStreamSynchronize(s->stream));
+  return QSV_OK;
+}
+
+qsv_status qsv_renormalize(qsv_state s, double* norm_out) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if ((st = select_device(s)) != QSV_OK) return st;
+  double* nd = nullptr;
+  if ((st = norm_dev(s, &nd)) != QSV_OK) return st;
+  double h = 0;
+  QSV_HIP(s, hipMemcpyAsync(&h, nd, sizeof(double), hipMemcpyDeviceToHost,
+                            s->stream));
+  QSV_HIP(s, hipStreamSynchronize(s->stream));
+  if (!(h > 0.0) || !std::isfinite(h))
+    return fail(QSV_ERR_INVALID_ARG, "state norm is zero or not finite");
+  QSV_HIP(s, launch_scale(s->prec, s->amp, s->n, nd, s->stream));
+  QSV_HIP(s, hipStreamSynchronize(s->stream));
+  if (norm_out) *norm_out = h;
+  return QSV_OK;
+}
+
+qsv_status qsv_marginal(qsv_state s, const int32_t* qubits, int32_t m,
+                        double* out_host) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if (!qubits || !out_host) return fail(QSV_ERR_INVALID_ARG, "null argument");
+  if (m < 1 || m > 20 || m > s->n)
+    return fail(QSV_ERR_INVALID_ARG, "m must be 1..min(20, n)");
+  uint64_t seen = 0;
+  for (int l = 0; l < m; ++l) {
+    if (qubits[l] < 0 || qubits[l] >= s->n)
+      return fail(QSV_ERR_INVALID_ARG, "qubit index out of range");
+    if (seen >> qubits[l] & 1)
+      return fail(QSV_ERR_INVALID_ARG, "duplicate marginal qubit");
+    seen |= uint64_t(1) << qubits[l];
+  }
+  if ((st = select_device(s)) != QSV_OK) return st;
+  const size_t part = (marginal_scratch_bytes(s->n, m) + 255) & ~size_t(255);
+  const size_t outb = sizeof(double) << m;
+  if ((st = ensure_scratch(s, part + outb)) != QSV_OK) return st;
+  double* od = reinterpret_cast<double*>(s->scratch + part);
+  QSV_HIP(s, launch_marginal(s->prec, s->amp, s->n, qubits, m,
+                             reinterpret_cast<double*>(s->scratch), od,
+                             s->stream));
+  QSV_HIP(s, hipMemcpyAsync(out_host, od, outb, hipMemcpyDeviceToHost,
+                            s->stream));
+  QSV_HIP(s, hipStreamSynchronize(s->stream));
+  return QSV_OK;
+}
+
+qsv_status qsv_sample(qsv_state s, uint64_t shots, uint64_t seed,
+                      uint64_t* out_host) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if (shots > (uint64_t(1) << 32))
+    return fail(QSV_ERR_INVALID_ARG, "n_shots must be <= 2^32");
+  if (shots && !out_host) return fail(QSV_ERR_INVALID_ARG, "null output");
+  if (shots == 0) return QSV_OK;
+  if ((st = select_device(s)) != QSV_OK) return st;
+  const size_t head = (sample_scratch_bytes(s->n, 0) + 255) & ~size_t(255);
+  if ((st = ensure_scratch(s, head + shots * sizeof(uint64_t))) != QSV_OK)
+    return st;
+  uint64_t* od = reinterpret_cast<uint64_t*>(s->scratch + head);
+  QSV_HIP(s, launch_sample(s->prec, s->amp, s->n, shots, seed, s->scratch, od,
+                           s->stream));
+  QSV_HIP(s, hipMemcpyAsync(out_host, od, shots * sizeof(uint64_t),
+                            hipMemcpyDeviceToHost, s->stream));
+  QSV_HIP(s, hipStreamSynchronize(s->stream));
+  return QSV_OK;
+}
+
+qsv_status qsv_get_amplitudes(qsv_state s, void* host_out) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if (!host_out) return fail(QSV_ERR_INVALID_ARG, "null output");
+  if ((st = select_device(s)) != QSV_OK) return st;
+  QSV_HIP(s, hipMemcpyAsync(host_out, s->amp, size_t(s->b) << s->n,
+                            hipMemcpyDeviceToHost, s->stream));
+  QSV_HIP(s, hipStreamSynchronize(s->stream));
+  return QSV_OK;
+}
+
+qsv_status qsv_set_amplitudes(qsv_state s, const void* host_in) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if (!host_in) return fail(QSV_ERR_INVALID_ARG, "null input");
+  if ((st = select_device(s)) != QSV_OK) return st;
+  QSV_HIP(s, hipMemcpyAsync(s->amp, host_in, size_t(s->b) << s->n,
+                            hipMemcpyHostToDevice, s->stream));
+  QSV_HIP(s, hipStreamSynchronize(s->stream));
+  return QSV_OK;
+}
+
+}  // extern "C"

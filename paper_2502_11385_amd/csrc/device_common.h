@@ -1,0 +1,101 @@
+// Device helpers shared by the HIP kernels (complex arithmetic, bit
+// insertion) and the launcher declarations used by the C ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "planner.h"
+#include "program.h"
+
+namespace qsv {
+
+template <typename T>
+struct CxT;
+template <>
+struct CxT<float> {
+  using type = float2;
+};
+template <>
+struct CxT<double> {
+  using type = double2;
+};
+
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+
+// a*x + b*y for complex a, b, x, y
+template <typename C>
+__device__ __forceinline__ C cmul2(C a, C x, C b, C y) {
+  C r;
+  r.x = a.x * x.x - a.y * x.y + b.x * y.x - b.y * y.y;
+  r.y = a.x * x.y + a.y * x.x + b.x * y.y + b.y * y.x;
+  return r;
+}
+
+// Insert a zero bit at position p (bits >= p move up by one).
+__device__ __forceinline__ uint64_t insert_zero64(uint64_t x, int p) {
+  const uint64_t lo = x & ((uint64_t(1) << p) - 1);
+  return ((x >> p) << (p + 1)) | lo;
+}
+__device__ __forceinline__ uint32_t insert_zero32(uint32_t x, int p) {
+  const uint32_t lo = x & ((uint32_t(1) << p) - 1);
+  return ((x >> p) << (p + 1)) | lo;
+}
+
+inline unsigned grid_blocks(uint64_t items, unsigned threads,
+                            unsigned cap = 1u << 20) {
+  uint64_t b = (items + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return unsigned(b);
+}
+
+// ------------------------------------------------------------ launchers
+// All launchers enqueue on `stream` and return hipGetLastError().
+// prec: 1 = complex64 (float2), 2 = complex128 (double2).
+
+hipError_t launch_fill_basis(int prec, void* amp, int n, uint64_t index,
+                             hipStream_t stream);
+// Plain dense gate; dev_matrix (2^k x 2^k, FP64) is required for k >= 3.
+hipError_t launch_dense(int prec, void* amp, int n, const HostGate& g,
+                        const double* dev_matrix, hipStream_t stream);
+// Plain diagonal gate (any k, controls).
+hipError_t launch_diag(int prec, void* amp, int n, const HostGate& g,
+                       hipStream_t stream);
+// One tile pass: pass/segs/ops point into the device program buffer;
+// L is the pass's tile size and rb its register bits.
+hipError_t launch_tile(int prec, int rb, void* amp, int n, int L,
+                       const TilePass* pass, const TileSeg* segs,
+                       const TileOp* ops, hipStream_t stream);
+// Build all fused unitaries (FP64, then rounded to FP32).
+hipError_t launch_fused_build(const FusedBlock* blocks, int n_blocks,
+                              const FusedGate* gates, double* mats64,
+                              float* mats32, hipStream_t stream);
+// Apply one fused block of width k on qubits q (host copy) with the device
+// matrix u (FP64 for c128, FP32 for c64).
+hipError_t launch_fused_apply(int prec, void* amp, int n, int k,
+                              const int32_t* q, const void* u,
+                              hipStream_t stream);
+
+// Reductions.  Scratch sizes are given by the *_scratch helpers (bytes).
+size_t norm_scratch_bytes(int n);
+hipError_t launch_probs(int prec, const void* amp, int n, void* out,
+                        int out_fp64, double* scratch, double* norm_dev,
+                        hipStream_t stream);
+hipError_t launch_scale(int prec, void* amp, int n, const double* norm_dev,
+                        hipStream_t stream);
+size_t marginal_scratch_bytes(int n, int m);
+hipError_t launch_marginal(int prec, const void* amp, int n,
+                           const int32_t* qubits, int m, double* scratch,
+                           double* out_dev, hipStream_t stream);
+size_t sample_scratch_bytes(int n, uint64_t shots);
+hipError_t launch_sample(int prec, const void* amp, int n, uint64_t shots,
+                         uint64_t seed, void* scratch, uint64_t* out_dev,
+                         hipStream_t stream);
+
+}  // namespace qsv

@@ -1,0 +1,281 @@
+// Plain per-gate kernels: basis-state initialisation, dense k-target gates
+// with controls (strided pair/quad/... updates), diagonal gates.
+//
+// A dense gate visits only the 2^(n-k-c) cosets whose control bits are 1:
+// thread g expands g by inserting zero bits at the sorted target and control
+// positions, sets the control bits, and updates the 2^k amplitudes at
+// base + sum_j bit_j(r) 2^targets[j].  Consecutive threads take consecutive
+// g, so for targets above the lowest few qubits both halves of every pair are
+// contiguous HBM streams 2^t amplitudes apart.
+#include "device_common.h"
+
+namespace qsv {
+
+// ---------------------------------------------------------------- init
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    fill_basis_kernel(typename CxT<T>::type* __restrict__ a, uint64_t count,
+                      uint64_t index) {
+  using C = typename CxT<T>::type;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+       i < count; i += stride) {
+    C v;
+    v.x = (i == index) ? T(1) : T(0);
+    v.y = T(0);
+    a[i] = v;
+  }
+}
+
+hipError_t launch_fill_basis(int prec, void* amp, int n, uint64_t index,
+                             hipStream_t stream) {
+  const uint64_t count = uint64_t(1) << n;
+  const unsigned blocks = grid_blocks(count, 256, 1u << 18);
+  if (prec == 1)
+    fill_basis_kernel<float><<<blocks, 256, 0, stream>>>(
+        static_cast<float2*>(amp), count, index);
+  else
+    fill_basis_kernel<double><<<blocks, 256, 0, stream>>>(
+        static_cast<double2*>(amp), count, index);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- dense
+
+struct DenseArgs {
+  uint64_t n_groups;
+  uint64_t cmask;
+  int32_t npos;
+  int32_t pad;
+  int32_t pos[40];   // sorted positions of targets and controls
+  int32_t tq[8];     // targets, targets[0] = least significant matrix bit
+  double m[32];      // matrix for k <= 2 (row-major, interleaved)
+  const double* mptr;  // matrix for k >= 3
+};
+
+// PTR: the matrix comes from device memory (FP64, rounded once to T while
+// staged in LDS); otherwise from the kernel arguments (k <= 2).
+template <typename T, int K, bool PTR>
+__global__ void __launch_bounds__(256)
+    dense_kernel(typename CxT<T>::type* __restrict__ a, DenseArgs args) {
+  using C = typename CxT<T>::type;
+  constexpr int D = 1 << K;
+  __shared__ C smat[PTR ? D * D : 1];
+  if constexpr (PTR) {
+    for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
+      C v;
+      v.x = T(args.mptr[2 * e]);
+      v.y = T(args.mptr[2 * e + 1]);
+      smat[e] = v;
+    }
+    __syncthreads();
+  }
+  uint64_t off[D];
+#pragma unroll
+  for (int r = 0; r < D; ++r) {
+    uint64_t o = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if (r >> j & 1) o |= uint64_t(1) << args.tq[j];
+    off[r] = o;
+  }
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+       g < args.n_groups; g += stride) {
+    uint64_t base = g;
+    for (int p = 0; p < args.npos; ++p) base = insert_zero64(base, args.pos[p]);
+    base |= args.cmask;
+    C v[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) v[r] = a[base + off[r]];
+    C w[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      T re = 0, im = 0;
+#pragma unroll
+      for (int s = 0; s < D; ++s) {
+        T mr, mi;
+        if constexpr (PTR) {
+          mr = smat[r * D + s].x;
+          mi = smat[r * D + s].y;
+        } else {
+          mr = T(args.m[2 * (r * D + s)]);
+          mi = T(args.m[2 * (r * D + s) + 1]);
+        }
+        re += mr * v[s].x - mi * v[s].y;
+        im += mr * v[s].y + mi * v[s].x;
+      }
+      w[r].x = re;
+      w[r].y = im;
+    }
+#pragma unroll
+    for (int r = 0; r < D; ++r) a[base + off[r]] = w[r];
+  }
+}
+
+template <typename T>
+static void dense_dispatch(T*, void* amp, int k, unsigned blocks,
+                           const DenseArgs& args, hipStream_t stream) {
+  using C = typename CxT<T>::type;
+  C* a = static_cast<C*>(amp);
+  const bool ptr = args.mptr != nullptr;
+  switch (k) {
+    case 1:
+      if (ptr)
+        dense_kernel<T, 1, true><<<blocks, 256, 0, stream>>>(a, args);
+      else
+        dense_kernel<T, 1, false><<<blocks, 256, 0, stream>>>(a, args);
+      break;
+    case 2:
+      if (ptr)
+        dense_kernel<T, 2, true><<<blocks, 256, 0, stream>>>(a, args);
+      else
+        dense_kernel<T, 2, false><<<blocks, 256, 0, stream>>>(a, args);
+      break;
+    case 3: dense_kernel<T, 3, true><<<blocks, 256, 0, stream>>>(a, args); break;
+    case 4: dense_kernel<T, 4, true><<<blocks, 256, 0, stream>>>(a, args); break;
+    case 5: dense_kernel<T, 5, true><<<blocks, 256, 0, stream>>>(a, args); break;
+  }
+}
+
+static void sorted_positions(uint64_t mask, int32_t* pos, int32_t* npos) {
+  int j = 0;
+  for (int q = 0; q < 64; ++q)
+    if (mask >> q & 1) pos[j++] = q;
+  *npos = j;
+}
+
+hipError_t launch_dense(int prec, void* amp, int n, const HostGate& g,
+                        const double* dev_matrix, hipStream_t stream) {
+  DenseArgs args = {};
+  args.n_groups = uint64_t(1) << (n - g.k - g.c);
+  args.cmask = g.cmask;
+  sorted_positions(g.tmask | g.cmask, args.pos, &args.npos);
+  for (int j = 0; j < g.k; ++j) args.tq[j] = g.t[j];
+  if (g.k <= 2) {
+    for (size_t e = 0; e < g.m.size(); ++e) args.m[e] = g.m[e];
+  } else {
+    if (!dev_matrix) return hipErrorInvalidValue;
+    args.mptr = dev_matrix;
+  }
+  const unsigned blocks = grid_blocks(args.n_groups, 256);
+  if (prec == 1)
+    dense_dispatch<float>(nullptr, amp, g.k, blocks, args, stream);
+  else
+    dense_dispatch<double>(nullptr, amp, g.k, blocks, args, stream);
+  return hipGetLastError();
+}
+
+// Dense k-qubit matrix from device memory on qubits q (no controls); used
+// for fused blocks with k <= 3.
+hipError_t launch_dense_dev(int prec, void* amp, int n, int k,
+                            const int32_t* q, const double* dev_matrix,
+                            hipStream_t stream) {
+  if (!dev_matrix || k < 1 || k > kMaxK) return hipErrorInvalidValue;
+  DenseArgs args = {};
+  args.n_groups = uint64_t(1) << (n - k);
+  uint64_t mask = 0;
+  for (int j = 0; j < k; ++j) {
+    args.tq[j] = q[j];
+    mask |= uint64_t(1) << q[j];
+  }
+  sorted_positions(mask, args.pos, &args.npos);
+  args.mptr = dev_matrix;
+  const unsigned blocks = grid_blocks(args.n_groups, 256);
+  if (prec == 1)
+    dense_dispatch<float>(nullptr, amp, k, blocks, args, stream);
+  else
+    dense_dispatch<double>(nullptr, amp, k, blocks, args, stream);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- diagonal
+
+struct DiagArgs {
+  uint64_t n_items;
+  uint64_t fixed_mask;  // bits forced to 1 (controls; + targets if masked)
+  int32_t npos;
+  int32_t k;
+  int32_t pos[40];      // sorted positions of the fixed bits
+  int32_t tq[8];
+  double d[64];         // diagonal entries (re, im); masked: d[0..1] = phase
+};
+
+// Masked phase: multiply the amplitudes whose bits in fixed_mask are all 1.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    diag_masked_kernel(typename CxT<T>::type* __restrict__ a, DiagArgs args) {
+  using C = typename CxT<T>::type;
+  C ph;
+  ph.x = T(args.d[0]);
+  ph.y = T(args.d[1]);
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+       g < args.n_items; g += stride) {
+    uint64_t i = g;
+    for (int p = 0; p < args.npos; ++p) i = insert_zero64(i, args.pos[p]);
+    i |= args.fixed_mask;
+    a[i] = cmul(a[i], ph);
+  }
+}
+
+// General diagonal: multiply by d[r(i)] where controls are satisfied.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    diag_table_kernel(typename CxT<T>::type* __restrict__ a, DiagArgs args) {
+  using C = typename CxT<T>::type;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+       g < args.n_items; g += stride) {
+    uint64_t i = g;
+    for (int p = 0; p < args.npos; ++p) i = insert_zero64(i, args.pos[p]);
+    i |= args.fixed_mask;
+    int r = 0;
+    for (int j = 0; j < args.k; ++j) r |= int((i >> args.tq[j]) & 1) << j;
+    C f;
+    f.x = T(args.d[2 * r]);
+    f.y = T(args.d[2 * r + 1]);
+    a[i] = cmul(a[i], f);
+  }
+}
+
+hipError_t launch_diag(int prec, void* amp, int n, const HostGate& g,
+                       hipStream_t stream) {
+  DiagArgs args = {};
+  args.k = g.k;
+  for (int j = 0; j < g.k; ++j) args.tq[j] = g.t[j];
+  const int d = 1 << g.k;
+  if (g.masked_phase) {
+    args.fixed_mask = g.tmask | g.cmask;
+    args.d[0] = g.m[2 * ((d - 1) * d + (d - 1))];
+    args.d[1] = g.m[2 * ((d - 1) * d + (d - 1)) + 1];
+  } else {
+    args.fixed_mask = g.cmask;
+    for (int r = 0; r < d; ++r) {
+      args.d[2 * r] = g.m[2 * (r * d + r)];
+      args.d[2 * r + 1] = g.m[2 * (r * d + r) + 1];
+    }
+  }
+  sorted_positions(args.fixed_mask, args.pos, &args.npos);
+  args.n_items = uint64_t(1) << (n - args.npos);
+  const unsigned blocks = grid_blocks(args.n_items, 256);
+  if (g.masked_phase) {
+    if (prec == 1)
+      diag_masked_kernel<float><<<blocks, 256, 0, stream>>>(
+          static_cast<float2*>(amp), args);
+    else
+      diag_masked_kernel<double><<<blocks, 256, 0, stream>>>(
+          static_cast<double2*>(amp), args);
+  } else {
+    if (prec == 1)
+      diag_table_kernel<float><<<blocks, 256, 0, stream>>>(
+          static_cast<float2*>(amp), args);
+    else
+      diag_table_kernel<double><<<blocks, 256, 0, stream>>>(
+          static_cast<double2*>(amp), args);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace qsv

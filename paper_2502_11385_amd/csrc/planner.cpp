@@ -1,0 +1,248 @@
+// Gate-fusion and tiling planner.
+//
+// The planner is the single-GPU counterpart of the transpile-time cache
+// blocking described in Section III.B: there, qubit reordering and inserted
+// swaps gather runs of gates onto the qubits inside one 2^nc chunk so that
+// they run without exchanging data.  Here a "chunk" is an LDS tile of 2^L
+// amplitudes (the coset of L tile qubits), and the planner reorders gates
+// that commute so that long runs of gates touch only the tile qubits; each
+// run then costs one HBM read and one HBM write of the state.  Diagonal gates
+// need no tile qubits at all: their factor depends only on the amplitude's
+// index, which every tile knows, so they join any pass.
+#include "planner.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace qsv {
+
+static inline int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+std::string resolve_options(int n, int bytes_per_amp, const int* v,
+                            PlanOptions* o) {
+  PlanOptions r;
+  r.strategy = v ? v[0] : 0;
+  r.tile_log2 = (v && v[1]) ? v[1] : (bytes_per_amp == 8 ? 12 : 11);
+  r.k_max = (v && v[2]) ? v[2] : 5;
+  r.low_qubits = (v && v[3]) ? v[3] : (bytes_per_amp == 8 ? 5 : 4);
+  r.reg_log2 = (v && v[4]) ? v[4] : 4;
+  if (r.strategy < 0 || r.strategy > 3) return "unknown strategy";
+  if (r.tile_log2 < 8 || r.tile_log2 > 13) return "tile_log2 must be 8..13";
+  if (r.k_max < 1 || r.k_max > kMaxK) return "k_max must be 1..5";
+  if (r.low_qubits < 0 || r.low_qubits > r.tile_log2 - 1)
+    return "low_qubits must be 0..tile_log2-1";
+  if (r.reg_log2 != 4 && r.reg_log2 != 5) return "reg_log2 must be 4 or 5";
+  if (r.reg_log2 > r.tile_log2 - 2) return "reg_log2 too large for tile";
+  if (bytes_per_amp == 16 && r.tile_log2 > 13)
+    return "tile too large for LDS";
+  (void)n;
+  *o = r;
+  return "";
+}
+
+std::string make_gate(int n, int k, int c, const int32_t* qubits,
+                      const double* matrix, HostGate* g) {
+  if (k < 1 || k > kMaxK) return "k must be 1..5";
+  if (c < 0 || k + c > n) return "too many targets + controls for n";
+  if (!qubits) return "null qubit list";
+  if (!matrix) return "null matrix";
+  uint64_t seen = 0;
+  for (int i = 0; i < k + c; ++i) {
+    int q = qubits[i];
+    if (q < 0 || q >= n) return "qubit index out of range";
+    if (seen >> q & 1) return "duplicate qubit among targets and controls";
+    seen |= 1ull << q;
+  }
+  HostGate h;
+  h.k = k;
+  h.c = c;
+  for (int i = 0; i < k; ++i) {
+    h.t[i] = qubits[i];
+    h.tmask |= 1ull << qubits[i];
+  }
+  for (int i = 0; i < c; ++i) {
+    h.ctl[i] = qubits[k + i];
+    h.cmask |= 1ull << qubits[k + i];
+  }
+  const int d = 1 << k;
+  h.m.assign(matrix, matrix + 2 * d * d);
+  for (double x : h.m)
+    if (!std::isfinite(x)) return "matrix has a non-finite entry";
+  bool diag = true;
+  for (int r = 0; r < d && diag; ++r)
+    for (int s = 0; s < d; ++s)
+      if (r != s && (h.m[2 * (r * d + s)] != 0.0 ||
+                     h.m[2 * (r * d + s) + 1] != 0.0)) {
+        diag = false;
+        break;
+      }
+  h.diagonal = diag;
+  bool mp = diag;
+  for (int r = 0; r + 1 < d && mp; ++r)
+    mp = h.m[2 * (r * d + r)] == 1.0 && h.m[2 * (r * d + r) + 1] == 0.0;
+  h.masked_phase = mp;
+  *g = std::move(h);
+  return "";
+}
+
+uint64_t plain_gate_bytes(const HostGate& g, int n, int b) {
+  int free_bits = n - g.c - (g.masked_phase ? g.k : 0);
+  return 2ull * (uint64_t(1) << free_bits) * uint64_t(b);
+}
+
+// One greedy scan over `pending` in list order.  A gate is taken when it
+// commutes with every gate skipped before it in this scan and the bits it
+// requires fit into `set` (at most `capacity` bits).  Taken gates keep their
+// relative order; skipped gates stay pending in their order.
+template <class Need, class Ok>
+static void greedy(const std::vector<HostGate>& G, std::vector<int>* pending,
+                   uint64_t* set, int capacity, Need need, Ok ok,
+                   std::vector<int>* taken) {
+  std::vector<int> rest;
+  uint64_t blk_touch = 0, blk_dense = 0;
+  for (int gi : *pending) {
+    const HostGate& g = G[gi];
+    bool take = false;
+    bool conflict = (g.dense() & blk_touch) || (g.touch() & blk_dense);
+    if (!conflict && ok(g)) {
+      uint64_t want = need(g) & ~*set;
+      if (popc(*set | want) <= capacity) {
+        *set |= want;
+        take = true;
+      }
+    }
+    if (take) {
+      taken->push_back(gi);
+    } else {
+      rest.push_back(gi);
+      blk_touch |= g.touch();
+      blk_dense |= g.dense();
+    }
+  }
+  pending->swap(rest);
+}
+
+static bool tileable(const HostGate& g) {
+  return g.diagonal ? (g.masked_phase || g.k <= 2) : g.k == 1;
+}
+
+static void add_plain(const std::vector<HostGate>& G, int gi, int n, int b,
+                      Plan* plan) {
+  Pass p;
+  p.kind = kPassPlain;
+  p.gates.push_back(gi);
+  p.qubits = G[gi].touch();
+  p.alg_bytes = plain_gate_bytes(G[gi], n, b);
+  plan->alg_bytes += p.alg_bytes;
+  plan->plain_passes++;
+  plan->passes.push_back(std::move(p));
+}
+
+static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
+                       const PlanOptions& o, Plan* plan) {
+  const int L = std::min(o.tile_log2, n);
+  const int RB = o.reg_log2;
+  const int m = std::min(o.low_qubits, L);
+  std::vector<int> pending(G.size());
+  for (size_t i = 0; i < G.size(); ++i) pending[i] = int(i);
+
+  while (!pending.empty()) {
+    if (!tileable(G[pending[0]])) {
+      add_plain(G, pending[0], n, b, plan);
+      pending.erase(pending.begin());
+      continue;
+    }
+    uint64_t Q = (m >= 64) ? ~0ull : ((1ull << m) - 1);
+    std::vector<int> taken;
+    greedy(G, &pending, &Q, L,
+           [](const HostGate& g) { return g.dense(); }, tileable, &taken);
+    // Fill the tile's qubit set up to exactly L qubits (lowest free first).
+    for (int q = 0; q < n && popc(Q) < L; ++q) Q |= 1ull << q;
+
+    Pass p;
+    p.kind = kPassTile;
+    p.L = L;
+    p.qubits = Q;
+    int local_of[64];
+    for (int q = 0, j = 0; q < n; ++q)
+      if (Q >> q & 1) {
+        p.q[j] = q;
+        local_of[q] = j++;
+      }
+    // Register segments: the same greedy scan over tile-local target bits
+    // with capacity RB; diagonal gates need no register bit.
+    std::vector<int> seg_pending = taken;
+    while (!seg_pending.empty()) {
+      uint64_t S = 0;
+      std::vector<int> seg_gates;
+      greedy(G, &seg_pending, &S, RB,
+             [&](const HostGate& g) -> uint64_t {
+               return g.diagonal ? 0 : (1ull << local_of[g.t[0]]);
+             },
+             [](const HostGate&) { return true; }, &seg_gates);
+      // Fill the register bits with the highest unused tile-local bits so
+      // that the low bits index lanes (contiguous HBM runs across lanes).
+      for (int lb = L - 1; lb >= 0 && popc(S) < RB; --lb) S |= 1ull << lb;
+      Pass::Seg sg;
+      for (int lb = 0, j = 0; lb < L; ++lb)
+        if (S >> lb & 1) sg.reg_bits[j++] = lb;
+      sg.gates = std::move(seg_gates);
+      p.segs.push_back(std::move(sg));
+    }
+    for (const auto& sg : p.segs)
+      p.gates.insert(p.gates.end(), sg.gates.begin(), sg.gates.end());
+    p.alg_bytes = 2ull * (uint64_t(1) << n) * uint64_t(b);
+    plan->alg_bytes += p.alg_bytes;
+    plan->tile_passes++;
+    plan->segments += int(p.segs.size());
+    plan->passes.push_back(std::move(p));
+  }
+}
+
+static void plan_fused(const std::vector<HostGate>& G, int n, int b,
+                       const PlanOptions& o, Plan* plan) {
+  const int K = std::min(o.k_max, n);
+  std::vector<int> pending(G.size());
+  for (size_t i = 0; i < G.size(); ++i) pending[i] = int(i);
+  auto fits = [K](const HostGate& g) { return popc(g.touch()) <= K; };
+  while (!pending.empty()) {
+    if (!fits(G[pending[0]])) {
+      add_plain(G, pending[0], n, b, plan);
+      pending.erase(pending.begin());
+      continue;
+    }
+    uint64_t S = 0;
+    std::vector<int> taken;
+    greedy(G, &pending, &S, K,
+           [](const HostGate& g) { return g.touch(); }, fits, &taken);
+    Pass p;
+    p.kind = kPassFused;
+    p.qubits = S;
+    p.fk = popc(S);
+    for (int q = 0, j = 0; q < n; ++q)
+      if (S >> q & 1) p.fq[j++] = q;
+    p.gates = std::move(taken);
+    p.alg_bytes = 2ull * (uint64_t(1) << n) * uint64_t(b);
+    plan->alg_bytes += p.alg_bytes;
+    plan->fused_passes++;
+    plan->passes.push_back(std::move(p));
+  }
+}
+
+void make_plan(const std::vector<HostGate>& G, int n, int b,
+               const PlanOptions& o, Plan* plan) {
+  *plan = Plan();
+  int strategy = o.strategy;
+  if (strategy == 0) strategy = (n >= o.reg_log2 + 2) ? 2 : 1;
+  if (strategy == 2 && n < o.reg_log2 + 2) strategy = 1;
+  if (strategy == 1) {
+    for (size_t i = 0; i < G.size(); ++i) add_plain(G, int(i), n, b, plan);
+  } else if (strategy == 2) {
+    plan_tiled(G, n, b, o, plan);
+  } else {
+    plan_fused(G, n, b, o, plan);
+  }
+}
+
+}  // namespace qsv

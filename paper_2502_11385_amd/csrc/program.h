@@ -1,0 +1,86 @@
+// Device program records shared by the host planner and the HIP kernels.
+//
+// A planned circuit is uploaded once per qsv_apply_fused call as one device
+// buffer holding these plain records; kernels read them with uniform loads.
+#pragma once
+#include <stdint.h>
+
+namespace qsv {
+
+constexpr int kMaxQubits = 34;
+constexpr int kMaxK = 5;
+constexpr int kMaxTileBits = 14;
+
+// Tile op kinds.
+enum : int32_t {
+  kOpDense1 = 0,  // 2x2 matrix on one register bit, optional controls
+  kOpDiag = 1,    // diagonal table on 1-2 qubits (local or outside the tile)
+  kOpPhase = 2    // multiply by m[0..1] where every bit of a mask is 1
+};
+
+// One gate inside a tile segment.
+//  kOpDense1: reg = index (0..RB-1) of the register bit holding the target;
+//             m = 2x2 complex matrix, row-major interleaved.
+//  kOpDiag:   dk targets (1 or 2); dbit[j] >= 0 is the tile-local bit of
+//             target j, dbit[j] < 0 means qubit (-1 - dbit[j]) outside the
+//             tile (its value is fixed per tile); m holds the 2^dk diagonal
+//             entries (re, im), entry index r = sum_j bit_j * 2^j.
+//  kOpPhase:  a diagonal gate whose entries are all 1 except the last
+//             (CZ, CP, S, T, P, multi-controlled phases): the amplitude is
+//             multiplied by the phase m[0..1] when all its target and
+//             control bits are 1; lctrl/gctrl then hold targets as well.
+//  lctrl: controls inside the tile as a mask of tile-local bits.
+//  gctrl: controls outside the tile as a mask of global qubits.
+struct alignas(16) TileOp {
+  int32_t kind;
+  int32_t reg;
+  int32_t dk;
+  int32_t dbit0;
+  int32_t dbit1;
+  uint32_t lctrl;
+  uint64_t gctrl;
+  double m[8];
+};
+
+// A run of ops executed with one register layout: the tile-local bits in
+// reg_bits[0..RB-1] (ascending) index each thread's registers; the other
+// tile-local bits, in ascending order, index the threads.
+struct alignas(16) TileSeg {
+  int32_t reg_bits[6];
+  int32_t op_begin;
+  int32_t op_end;
+};
+
+// One tile pass: 2^L amplitudes per tile, tile-local bit b is global qubit
+// q[b] (ascending).  Tiles are the cosets of the other n - L qubits.
+struct alignas(16) TilePass {
+  int32_t L;
+  int32_t nseg;
+  int32_t seg_begin;
+  int32_t pad;
+  int32_t q[16];
+};
+
+// One gate of a fused block, in the block's local qubit numbering
+// (block qubit j = j-th smallest qubit of the block).
+struct alignas(16) FusedGate {
+  int32_t k;          // targets (1..5)
+  int32_t c;          // controls
+  int32_t t[5];
+  int32_t ctl[5];
+  int64_t m_offset;   // offset (in doubles) of the 2^k x 2^k matrix
+};
+
+// One fused block: apply the product of its gates, a 2^k x 2^k unitary on
+// block qubits q[0..k-1].
+struct alignas(16) FusedBlock {
+  int32_t k;
+  int32_t n_gates;
+  int32_t gate_begin;
+  int32_t pad;
+  int64_t u64_offset;  // FP64 product, 2^k x 2^k complex (in doubles)
+  int64_t u32_offset;  // the same rounded once to FP32 (in floats)
+  int32_t q[8];
+};
+
+}  // namespace qsv

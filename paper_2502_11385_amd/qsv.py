@@ -1,0 +1,371 @@
+"""ctypes binding of libqsv.so (argument marshalling only).
+
+Every call maps one-to-one onto the C ABI declared in ``include/qsv.h``; all
+arithmetic runs in the HIP library.  PyTorch is used only for device
+buffers and streams.  If the library has not been built this module raises
+at import: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqsv.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first "
+        "(python -m paper_2502_11385_amd.build)")
+
+# PyTorch ships its own HIP runtime.  Importing it first makes libqsv bind
+# to that same runtime (same soname) instead of mapping a second one, so that
+# tensors, streams and the library share one device context.
+import torch  # noqa: E402,F401
+
+_lib = C.CDLL(LIB_PATH)
+
+QSV_OK = 0
+QSV_ERR_INVALID_ARG = 1
+QSV_ERR_OUT_OF_MEMORY = 2
+QSV_ERR_DEVICE = 3
+QSV_ERR_UNSUPPORTED = 4
+QSV_ERR_BUDGET = 5
+QSV_C64 = 1
+QSV_C128 = 2
+PLAN_AUTO, PLAN_PLAIN, PLAN_TILED, PLAN_FUSED = 0, 1, 2, 3
+MAX_QUBITS = 34
+
+EXPORTED = [
+    "qsv_alloc", "qsv_wrap", "qsv_free", "qsv_init_basis", "qsv_apply_gate",
+    "qsv_apply_fused", "qsv_last_plan_stats", "qsv_plan_describe",
+    "qsv_gate_matrix", "qsv_probabilities", "qsv_norm", "qsv_renormalize",
+    "qsv_marginal", "qsv_sample", "qsv_get_amplitudes", "qsv_set_amplitudes",
+    "qsv_info", "qsv_sync", "qsv_last_error", "qsv_version",
+    "qsv_set_profiling", "qsv_pass_times",
+]
+
+
+class QsvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"qsv status {status}: {msg}")
+        self.status = status
+
+
+class qsv_circuit(C.Structure):
+    _fields_ = [("n_gates", C.c_size_t),
+                ("k", C.POINTER(C.c_int32)),
+                ("c", C.POINTER(C.c_int32)),
+                ("qubits", C.POINTER(C.c_int32)),
+                ("matrices", C.POINTER(C.c_double))]
+
+
+class qsv_fuse_opts(C.Structure):
+    _fields_ = [("strategy", C.c_int32), ("tile_log2", C.c_int32),
+                ("k_max", C.c_int32), ("low_qubits", C.c_int32),
+                ("reg_log2", C.c_int32)]
+
+
+_p = C.c_void_p
+_i32 = C.c_int32
+_u64 = C.c_uint64
+_pi32 = C.POINTER(C.c_int32)
+_pd = C.POINTER(C.c_double)
+_pu64 = C.POINTER(C.c_uint64)
+
+_SIGS = {
+    "qsv_alloc": [_i32, _i32, _p, C.POINTER(_p)],
+    "qsv_wrap": [_i32, _i32, _p, C.c_size_t, _p, C.POINTER(_p)],
+    "qsv_free": [_p],
+    "qsv_init_basis": [_p, _u64],
+    "qsv_apply_gate": [_p, _pi32, _i32, _pi32, _i32, _pd],
+    "qsv_apply_fused": [_p, C.POINTER(qsv_circuit), C.POINTER(qsv_fuse_opts)],
+    "qsv_last_plan_stats": [_p, _pu64, _i32],
+    "qsv_plan_describe": [C.POINTER(qsv_circuit), _i32, _i32,
+                          C.POINTER(qsv_fuse_opts), _pi32, _pi32, _pi32,
+                          _pu64, _pi32],
+    "qsv_gate_matrix": [C.c_char_p, _pd, _i32, _pd, _pi32],
+    "qsv_probabilities": [_p, _p, _i32],
+    "qsv_norm": [_p, _pd],
+    "qsv_renormalize": [_p, _pd],
+    "qsv_marginal": [_p, _pi32, _i32, _pd],
+    "qsv_sample": [_p, _u64, _u64, _pu64],
+    "qsv_get_amplitudes": [_p, _p],
+    "qsv_set_amplitudes": [_p, _p],
+    "qsv_info": [_p, C.POINTER(_p), _pi32, _pi32],
+    "qsv_sync": [_p],
+    "qsv_set_profiling": [_p, _i32],
+    "qsv_pass_times": [_p, C.POINTER(C.c_float), _pi32, _i32, _pi32],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+_lib.qsv_last_error.restype = C.c_char_p
+_lib.qsv_last_error.argtypes = []
+_lib.qsv_version.restype = C.c_char_p
+_lib.qsv_version.argtypes = []
+
+
+def lib():
+    return _lib
+
+
+def last_error() -> str:
+    return _lib.qsv_last_error().decode()
+
+
+def version() -> str:
+    return _lib.qsv_version().decode()
+
+
+def _check(status: int) -> None:
+    if status != QSV_OK:
+        raise QsvError(status, last_error())
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+# ---------------------------------------------------------------- gates
+
+def gate_matrix(name: str, params: Sequence[float] = ()) -> np.ndarray:
+    """Standard 2x2 gate matrix from the library (complex128)."""
+    p = np.asarray(params, dtype=np.float64)
+    out = np.zeros(8, dtype=np.float64)
+    k = C.c_int32(0)
+    _check(_lib.qsv_gate_matrix(name.encode(), _ptr(p, C.c_double) if p.size
+                                else None, int(p.size), _ptr(out, C.c_double),
+                                C.byref(k)))
+    return (out[0::2] + 1j * out[1::2]).reshape(2, 2)
+
+
+class Circuit:
+    """A gate list flattened into the arrays of ``qsv_circuit``."""
+
+    def __init__(self):
+        self.k, self.c, self.qubits, self.mats = [], [], [], []
+        self._cache = {}
+
+    def add(self, targets: Sequence[int], matrix, controls: Sequence[int] = ()):
+        m = np.asarray(matrix, dtype=np.complex128)
+        self.k.append(len(targets))
+        self.c.append(len(controls))
+        self.qubits.extend(int(q) for q in targets)
+        self.qubits.extend(int(q) for q in controls)
+        self.mats.append(np.ascontiguousarray(m).view(np.float64).reshape(-1))
+        self._arrays = None
+        return self
+
+    def _std(self, name, params):
+        key = (name, tuple(params))
+        m = self._cache.get(key)
+        if m is None:
+            m = gate_matrix(name, params)
+            self._cache[key] = m
+        return m
+
+    def add_named(self, name: str, qubits: Sequence[int],
+                  params: Sequence[float] = ()):
+        """Named gates of the synthetic workloads: one-qubit gates by name;
+        cx(c, t) = X on t controlled by c; cz(a, b) = Z on b controlled by a;
+        cp(a, b; l) = P(l) on b controlled by a."""
+        if name == "cx":
+            return self.add([qubits[1]], self._std("x", ()), [qubits[0]])
+        if name == "cz":
+            return self.add([qubits[1]], self._std("z", ()), [qubits[0]])
+        if name == "cp":
+            return self.add([qubits[1]], self._std("p", params), [qubits[0]])
+        return self.add([qubits[0]], self._std(name, params))
+
+    @classmethod
+    def from_gates(cls, gates: Iterable) -> "Circuit":
+        c = cls()
+        for g in gates:
+            c.add_named(g.name, g.qubits, g.params)
+        return c
+
+    def __len__(self):
+        return len(self.k)
+
+    def arrays(self):
+        if getattr(self, "_arrays", None) is None:
+            k = np.asarray(self.k, dtype=np.int32)
+            c = np.asarray(self.c, dtype=np.int32)
+            q = np.asarray(self.qubits, dtype=np.int32)
+            m = (np.concatenate(self.mats) if self.mats
+                 else np.zeros(0, np.float64))
+            self._arrays = (k, c, q, np.ascontiguousarray(m))
+        return self._arrays
+
+    def struct(self) -> qsv_circuit:
+        k, c, q, m = self.arrays()
+        return qsv_circuit(len(k), _ptr(k, C.c_int32), _ptr(c, C.c_int32),
+                           _ptr(q, C.c_int32), _ptr(m, C.c_double))
+
+
+def fuse_opts(strategy: int = 0, tile_log2: int = 0, k_max: int = 0,
+              low_qubits: int = 0, reg_log2: int = 0) -> qsv_fuse_opts:
+    return qsv_fuse_opts(strategy, tile_log2, k_max, low_qubits, reg_log2)
+
+
+def plan_describe(circ: Circuit, n: int, prec: int = QSV_C64,
+                  opts: Optional[qsv_fuse_opts] = None):
+    """Host-only planner dry run: (gate_pass, gate_order, pass_kind,
+    pass_qubits) as NumPy arrays."""
+    g = max(len(circ), 1)
+    gate_pass = np.zeros(g, np.int32)
+    gate_order = np.zeros(g, np.int32)
+    pass_kind = np.zeros(g, np.int32)
+    pass_qubits = np.zeros(g, np.uint64)
+    npass = C.c_int32(0)
+    st = circ.struct()
+    _check(_lib.qsv_plan_describe(
+        C.byref(st), n, prec, C.byref(opts) if opts is not None else None,
+        _ptr(gate_pass, C.c_int32), _ptr(gate_order, C.c_int32),
+        _ptr(pass_kind, C.c_int32), _ptr(pass_qubits, C.c_uint64),
+        C.byref(npass)))
+    p = npass.value
+    n_g = len(circ)
+    return gate_pass[:n_g], gate_order[:n_g], pass_kind[:p], pass_qubits[:p]
+
+
+# ---------------------------------------------------------------- states
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    h = getattr(stream, "cuda_stream", stream)
+    return int(h) if h else None
+
+
+class State:
+    """A 2^n complex state on the device (owned, or wrapping a tensor)."""
+
+    def __init__(self, n: int, prec: int = QSV_C64, stream=None,
+                 tensor=None):
+        self.n = n
+        self.prec = prec
+        self._h = C.c_void_p()
+        self._tensor = tensor
+        sh = _stream_handle(stream)
+        if tensor is None:
+            _check(_lib.qsv_alloc(n, prec, sh, C.byref(self._h)))
+        else:
+            nbytes = tensor.numel() * tensor.element_size()
+            _check(_lib.qsv_wrap(n, prec, tensor.data_ptr(), nbytes, sh,
+                                 C.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def amp_dtype(self):
+        return np.complex64 if self.prec == QSV_C64 else np.complex128
+
+    def free(self):
+        if self._h:
+            _check(_lib.qsv_free(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._h:
+                _lib.qsv_free(self._h)
+        except Exception:
+            pass
+
+    def device_ptr(self) -> int:
+        p = C.c_void_p()
+        _check(_lib.qsv_info(self._h, C.byref(p), None, None))
+        return p.value
+
+    def init_basis(self, index: int = 0):
+        _check(_lib.qsv_init_basis(self._h, int(index)))
+
+    def apply_gate(self, targets, matrix, controls=()):
+        t = np.asarray(targets, dtype=np.int32)
+        c = np.asarray(controls, dtype=np.int32)
+        m = np.ascontiguousarray(np.asarray(matrix, dtype=np.complex128)
+                                 ).view(np.float64).reshape(-1)
+        _check(_lib.qsv_apply_gate(self._h, _ptr(t, C.c_int32), len(t),
+                                   _ptr(c, C.c_int32) if len(c) else None,
+                                   len(c), _ptr(m, C.c_double)))
+
+    def apply_fused(self, circ: Circuit, opts: Optional[qsv_fuse_opts] = None):
+        st = circ.struct()
+        _check(_lib.qsv_apply_fused(self._h, C.byref(st),
+                                    C.byref(opts) if opts is not None else None))
+
+    def plan_stats(self) -> dict:
+        out = np.zeros(8, np.uint64)
+        _check(_lib.qsv_last_plan_stats(self._h, _ptr(out, C.c_uint64), 8))
+        keys = ("passes", "gates", "alg_bytes", "tile_passes", "plain_passes",
+                "fused_passes", "segments", "plan_ns")
+        return {k: int(v) for k, v in zip(keys, out)}
+
+    def set_profiling(self, enable: bool):
+        _check(_lib.qsv_set_profiling(self._h, 1 if enable else 0))
+
+    def pass_times(self, cap: int = 1 << 16):
+        """(ms per pass, kind per pass) of the last apply_fused."""
+        ms = np.zeros(cap, np.float32)
+        kinds = np.zeros(cap, np.int32)
+        cnt = C.c_int32(0)
+        _check(_lib.qsv_pass_times(self._h, _ptr(ms, C.c_float),
+                                   _ptr(kinds, C.c_int32), cap, C.byref(cnt)))
+        m = min(cap, cnt.value)
+        return ms[:m], kinds[:m]
+
+    def probabilities_into(self, out_ptr: int, fp64: bool):
+        _check(_lib.qsv_probabilities(self._h, out_ptr, 1 if fp64 else 0))
+
+    def probabilities(self, fp64: bool = True):
+        """Device probability vector as a torch tensor (caller-owned)."""
+        import torch
+        dt = torch.float64 if fp64 else torch.float32
+        out = torch.empty(1 << self.n, dtype=dt, device="cuda")
+        self.probabilities_into(out.data_ptr(), fp64)
+        return out
+
+    def norm(self) -> float:
+        v = C.c_double(0)
+        _check(_lib.qsv_norm(self._h, C.byref(v)))
+        return v.value
+
+    def renormalize(self) -> float:
+        v = C.c_double(0)
+        _check(_lib.qsv_renormalize(self._h, C.byref(v)))
+        return v.value
+
+    def marginal(self, qubits: Sequence[int]) -> np.ndarray:
+        q = np.asarray(qubits, dtype=np.int32)
+        out = np.zeros(1 << len(q), np.float64)
+        _check(_lib.qsv_marginal(self._h, _ptr(q, C.c_int32), len(q),
+                                 _ptr(out, C.c_double)))
+        return out
+
+    def sample(self, shots: int, seed: int) -> np.ndarray:
+        out = np.zeros(max(int(shots), 1), np.uint64)
+        _check(_lib.qsv_sample(self._h, int(shots), int(seed),
+                               _ptr(out, C.c_uint64)))
+        return out[:shots]
+
+    def get(self) -> np.ndarray:
+        out = np.zeros(1 << self.n, self.amp_dtype)
+        _check(_lib.qsv_get_amplitudes(self._h, out.ctypes.data))
+        return out
+
+    def set(self, psi: np.ndarray):
+        a = np.ascontiguousarray(np.asarray(psi, dtype=self.amp_dtype))
+        if a.size != 1 << self.n:
+            raise ValueError("wrong length")
+        _check(_lib.qsv_set_amplitudes(self._h, a.ctypes.data))
+
+    def sync(self):
+        _check(_lib.qsv_sync(self._h))

@@ -1,0 +1,130 @@
+"""The host planner (no GPU): its pass list, replayed by the oracle, gives the
+same state as the gate list in order; tile passes respect the tile's qubit
+set and size; fused blocks respect k_max; the block products, multiplied in
+NumPy here and applied by the oracle, reproduce the circuit."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from circuits import Gate, layered_circuit, qft_style_circuit, random_state
+from paper_2502_11385_amd import qsv
+
+
+def _mixed(n, count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        kind = int(rng.integers(0, 8))
+        a, b = (int(v) for v in rng.choice(n, 2, replace=False))
+        ang = [float(v) for v in rng.uniform(0, 2 * math.pi, 3)]
+        out.append([Gate("u3", (a,), tuple(ang)), Gate("h", (a,)),
+                    Gate("s", (a,)), Gate("p", (a,), (ang[0],)),
+                    Gate("cx", (a, b)), Gate("cz", (a, b)),
+                    Gate("cp", (a, b), (ang[1],)), Gate("x", (a,))][kind])
+    return out
+
+
+def _specs(gates):
+    return [oracle.gate_spec(g.name, g.qubits, g.params) for g in gates]
+
+
+def _replay(n, specs, order, v):
+    psi = v.copy()
+    for gi in order:
+        t, c, u = specs[gi]
+        psi = oracle.apply_gate(psi, n, u, t, c)
+    return psi
+
+
+CASES = [
+    ("layered", 8, lambda: layered_circuit(8, 6, 1)),
+    ("layered14", 14, lambda: layered_circuit(14, 5, 2)),
+    ("qft", 9, lambda: qft_style_circuit(9, 4, tail_layers=2)[1]),
+    ("mixed", 10, lambda: _mixed(10, 120, 5)),
+]
+
+
+@pytest.mark.parametrize("strategy", [qsv.PLAN_PLAIN, qsv.PLAN_TILED,
+                                      qsv.PLAN_FUSED])
+@pytest.mark.parametrize("name,n,make", CASES)
+def test_plan_order_is_equivalent(strategy, name, n, make):
+    gates = make()
+    circ = qsv.Circuit.from_gates(gates)
+    for opts in (qsv.fuse_opts(strategy=strategy),
+                 qsv.fuse_opts(strategy=strategy, tile_log2=8, k_max=3,
+                               low_qubits=2, reg_log2=5)):
+        gp, order, kinds, pq = qsv.plan_describe(circ, n, qsv.QSV_C64, opts)
+        assert sorted(order.tolist()) == list(range(len(gates)))
+        # passes are applied in order; gates of one pass are contiguous
+        assert np.all(np.diff(gp[order]) >= 0)
+        specs = _specs(gates)
+        v = random_state(n, 3)
+        want = _replay(n, specs, range(len(gates)), v)
+        got = _replay(n, specs, order, v)
+        assert np.max(np.abs(got - want)) < 1e-12
+        if strategy == qsv.PLAN_PLAIN:
+            assert len(kinds) == len(gates) and np.all(kinds == 1)
+
+
+@pytest.mark.parametrize("name,n,make", CASES)
+def test_tile_pass_structure(name, n, make):
+    gates = make()
+    circ = qsv.Circuit.from_gates(gates)
+    for L, m in ((10, 5), (8, 2), (12, 4)):
+        opts = qsv.fuse_opts(strategy=qsv.PLAN_TILED, tile_log2=L,
+                             low_qubits=m)
+        gp, order, kinds, pq = qsv.plan_describe(circ, n, qsv.QSV_C64, opts)
+        Le = min(L, n)
+        for p, mask in enumerate(pq):
+            if kinds[p] != 2:
+                continue
+            mask = int(mask)
+            assert bin(mask).count("1") == Le
+            assert mask & ((1 << min(m, Le)) - 1) == (1 << min(m, Le)) - 1
+        for gi, g in enumerate(gates):
+            t, c, u = oracle.gate_spec(g.name, g.qubits, g.params)
+            p = gp[gi]
+            if kinds[p] == 2 and not np.allclose(u, np.diag(np.diag(u))):
+                for q in t:   # dense targets must be tile qubits
+                    assert int(pq[p]) >> q & 1
+
+
+@pytest.mark.parametrize("kmax", [2, 3, 5])
+@pytest.mark.parametrize("name,n,make", CASES)
+def test_fused_blocks_reproduce_circuit(kmax, name, n, make):
+    gates = make()
+    circ = qsv.Circuit.from_gates(gates)
+    opts = qsv.fuse_opts(strategy=qsv.PLAN_FUSED, k_max=kmax)
+    gp, order, kinds, pq = qsv.plan_describe(circ, n, qsv.QSV_C128, opts)
+    specs = _specs(gates)
+    v = random_state(n, 9)
+    want = _replay(n, specs, range(len(gates)), v)
+    psi = v.copy()
+    for p in range(len(kinds)):
+        members = [gi for gi in order if gp[gi] == p]
+        qs = [q for q in range(n) if int(pq[p]) >> q & 1]
+        assert kinds[p] == 3 and len(qs) <= kmax
+        k = len(qs)
+        # block product in NumPy: embed each member on the block's qubits
+        u = np.eye(1 << k, dtype=complex)
+        for gi in members:
+            t, c, g = specs[gi]
+            assert set(t) | set(c) <= set(qs)
+            u = oracle.embed(k, g, [qs.index(x) for x in t],
+                             [qs.index(x) for x in c]) @ u
+        psi = oracle.apply_gate(psi, n, u, qs)
+    assert np.max(np.abs(psi - want)) < 1e-12
+
+
+def test_pass_counts_30q_layered():
+    gates = layered_circuit(30, 40, 30)
+    circ = qsv.Circuit.from_gates(gates)
+    _, _, kinds, _ = qsv.plan_describe(circ, 30, qsv.QSV_C64,
+                                       qsv.fuse_opts(strategy=qsv.PLAN_TILED))
+    # 1780 gates; the tiled plan needs far fewer full passes
+    assert len(kinds) < 200
+    _, _, fk, _ = qsv.plan_describe(circ, 30, qsv.QSV_C64,
+                                    qsv.fuse_opts(strategy=qsv.PLAN_FUSED))
+    assert len(fk) < 1780
