@@ -27,13 +27,17 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-function"]
 # Packed FP32 instructions stay disabled on this target.
 DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Keep switch arms over register indices separate: merging them turns
+# constant register-array indices into dynamic ones, which forces the
+# register-resident tile into scratch memory.
+NO_SINK = ["-mllvm", "-simplifycfg-sink-common=false"]
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC] + COMMON + DEVICE
     if src.endswith(".hip"):
-        cmd += ["-x", "hip"]
+        cmd += ["-x", "hip"] + NO_SINK
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -429,6 +429,7 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
               op.m[2 * r + 1] = g.m[2 * (r * d + r) + 1];
             }
           }
+          for (int e = 0; e < 8; ++e) op.mf[e] = float(op.m[e]);
           tops.push_back(op);
         }
         ts.op_end = int32_t(tops.size());

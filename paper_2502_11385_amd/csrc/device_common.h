@@ -37,6 +37,16 @@ __device__ __forceinline__ C cmul2(C a, C x, C b, C y) {
   return r;
 }
 
+// Component-wise select.  A conditional operator on the HIP vector structs
+// selects between their addresses, which keeps register arrays in memory.
+template <typename C>
+__device__ __forceinline__ C csel(bool c, C a, C b) {
+  C r;
+  r.x = c ? a.x : b.x;
+  r.y = c ? a.y : b.y;
+  return r;
+}
+
 // Insert a zero bit at position p (bits >= p move up by one).
 __device__ __forceinline__ uint64_t insert_zero64(uint64_t x, int p) {
   const uint64_t lo = x & ((uint64_t(1) << p) - 1);

@@ -208,7 +208,9 @@ __global__ void __launch_bounds__(256)
 }
 
 // Complex128, k = 4 or 5: FP64 MFMA 16x16x4.  Per wave: 16 groups; lane
-// l = 16 h + j holds group j and the amplitudes s = 4 e + h.
+// l = 16 h + j holds group j and the amplitudes s = 4 e + h.  Operand
+// layout: A[i = l % 16][k = l / 16], B[k = l / 16][j = l % 16]; the result
+// D[i][j] sits in lane 16 (i % 4) + j, register i / 4.
 template <int K>
 __global__ void __launch_bounds__(256)
     fused_mfma_c128_kernel(double2* __restrict__ amp, FusedArgs args,
@@ -238,13 +240,14 @@ __global__ void __launch_bounds__(256)
   uint64_t in_off[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) in_off[e] = deposit_bits(4 * e + h, args.q, K);
+  // Result register v of lane (h, j) holds row h + 4 v of its tile.
   constexpr int OUT_T = NT / 2;
   uint64_t out_off[OUT_T][4];
 #pragma unroll
   for (int T = 0; T < OUT_T; ++T)
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      out_off[T][v] = deposit_bits(16 * T + 4 * h + v, args.q, K);
+      out_off[T][v] = deposit_bits(16 * T + h + 4 * v, args.q, K);
 
   const uint64_t wave = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const uint64_t nwaves = (uint64_t(gridDim.x) * blockDim.x) >> 6;

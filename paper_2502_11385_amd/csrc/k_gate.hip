@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(256)
     C v[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) v[r] = a[base + off[r]];
-    C w[D];
+    // All inputs are in registers, so each output can be stored at once.
 #pragma unroll
     for (int r = 0; r < D; ++r) {
       T re = 0, im = 0;
@@ -106,11 +106,11 @@ __global__ void __launch_bounds__(256)
         re += mr * v[s].x - mi * v[s].y;
         im += mr * v[s].y + mi * v[s].x;
       }
-      w[r].x = re;
-      w[r].y = im;
+      C w;
+      w.x = re;
+      w.y = im;
+      a[base + off[r]] = w;
     }
-#pragma unroll
-    for (int r = 0; r < D; ++r) a[base + off[r]] = w[r];
   }
 }
 

@@ -45,8 +45,8 @@ __device__ __forceinline__ void dense1_regs(C* a, T m0r, T m0i, T m1r, T m1i,
     y1.y = m2r * x0.y + m2i * x0.x + m3r * x1.y + m3i * x1.x;
     if constexpr (CTRL) {
       const bool on = ((rt | lr[j]) & lctrl) == lctrl;
-      a[j] = on ? y0 : x0;
-      a[j1] = on ? y1 : x1;
+      a[j] = csel(on, y0, x0);
+      a[j1] = csel(on, y1, x1);
     } else {
       a[j] = y0;
       a[j1] = y1;
@@ -124,8 +124,10 @@ __device__ __forceinline__ void relayout(C* a, C* lds, const Layout<RB>& from,
   __syncthreads();
 }
 
+// At most 512 threads per tile (L - RB <= 9), which leaves up to 256 VGPRs
+// per lane for the register-resident tile.
 template <typename T, int RB>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(512)
     tile_kernel(typename CxT<T>::type* __restrict__ amp,
                 const TilePass* __restrict__ pass,
                 const TileSeg* __restrict__ segs,
@@ -188,7 +190,12 @@ __global__ void __launch_bounds__(1024)
       if (kind == kOpDense1) {
         T m[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) m[e] = T(op->m[e]);
+        for (int e = 0; e < 8; ++e) {
+          if constexpr (sizeof(T) == 4)
+            m[e] = op->mf[e];
+          else
+            m[e] = op->m[e];
+        }
         if (lctrl)
           dense1_dispatch<R, true>(op->reg, a, m, rt, lr, lctrl);
         else
@@ -201,7 +208,7 @@ __global__ void __launch_bounds__(1024)
         for (int j = 0; j < R; ++j) {
           const bool on = ((rt | lr[j]) & lctrl) == lctrl;
           const C y = cmul(a[j], ph);
-          a[j] = on ? y : a[j];
+          a[j] = csel(on, y, a[j]);
         }
       } else {  // kOpDiag
         const int dk = op->dk;
@@ -222,12 +229,12 @@ __global__ void __launch_bounds__(1024)
           const uint32_t b0 = d0 >= 0 ? (r >> (d0 & 31)) & 1u : g0;
           const uint32_t b1 =
               dk > 1 ? (d1 >= 0 ? (r >> (d1 & 31)) & 1u : g1) : 0u;
-          const C f01 = b0 ? t[1] : t[0];
-          const C f23 = b0 ? t[3] : t[2];
-          const C f = b1 ? f23 : f01;
+          const C f01 = csel(b0 != 0, t[1], t[0]);
+          const C f23 = csel(b0 != 0, t[3], t[2]);
+          const C f = csel(b1 != 0, f23, f01);
           const bool on = (r & lctrl) == lctrl;
           const C y = cmul(a[j], f);
-          a[j] = on ? y : a[j];
+          a[j] = csel(on, y, a[j]);
         }
       }
     }
@@ -267,7 +274,7 @@ static hipError_t tile_launch(void* amp, int n, int L, const TilePass* pass,
 hipError_t launch_tile(int prec, int rb, void* amp, int n, int L,
                        const TilePass* pass, const TileSeg* segs,
                        const TileOp* ops, hipStream_t stream) {
-  if (L - rb < 0 || L - rb > 10 || n - L > 31) return hipErrorInvalidValue;
+  if (L - rb < 0 || L - rb > 9 || n - L > 31) return hipErrorInvalidValue;
   if (prec == 1)
     return rb == 4 ? tile_launch<float, 4>(amp, n, L, pass, segs, ops, stream)
                    : tile_launch<float, 5>(amp, n, L, pass, segs, ops, stream);

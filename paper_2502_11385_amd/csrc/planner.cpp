@@ -34,8 +34,8 @@ std::string resolve_options(int n, int bytes_per_amp, const int* v,
     return "low_qubits must be 0..tile_log2-1";
   if (r.reg_log2 != 4 && r.reg_log2 != 5) return "reg_log2 must be 4 or 5";
   if (r.reg_log2 > r.tile_log2 - 2) return "reg_log2 too large for tile";
-  if (bytes_per_amp == 16 && r.tile_log2 > 13)
-    return "tile too large for LDS";
+  if (bytes_per_amp == 16 && r.reg_log2 > 4)
+    return "reg_log2 must be 4 for complex128 (register budget)";
   (void)n;
   *o = r;
   return "";

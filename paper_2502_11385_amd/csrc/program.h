@@ -40,6 +40,7 @@ struct alignas(16) TileOp {
   uint32_t lctrl;
   uint64_t gctrl;
   double m[8];
+  float mf[8];  // m rounded to FP32 (complex64 states)
 };
 
 // A run of ops executed with one register layout: the tile-local bits in
