@@ -83,6 +83,80 @@ def run_cpu_baseline(budget_s: float) -> dict:
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+# --------------------------------------------------------------- batch leg
+
+BATCH_COUNT, BATCH_SEED = 4096, 4096
+PROLOGUE = {"0": [], "1": ["x"], "+": ["h"], "+i": ["h", "s"]}
+EPILOGUE = {"I": [], "X": ["h"], "Y": ["sdg", "h"]}
+
+
+def batch_leg(qsv, torch, np, steps: int, per_circuit: bool) -> dict:
+    """4096 cut variants (widths 10..20, depths 10..60), complex64: one
+    persistent launch (autotuned, replayed from a hipGraph) against one
+    library call sequence per circuit (init, planned passes, probabilities)
+    on the whole GPU."""
+    from circuits import Gate, batch_variants
+    t0 = time.perf_counter()
+    vs = batch_variants(BATCH_COUNT, seed=BATCH_SEED)
+    t1 = time.perf_counter()
+    b = qsv.Batch(vs, prec=qsv.QSV_C64, autotune=True, use_graph=True)
+    t2 = time.perf_counter()
+    out = b.output()
+    b.launch(out)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        b.launch(out)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    st = b.stats()
+    res = {"workload": (f"{BATCH_COUNT} cut variants, widths 10..20, depths "
+                        f"10..60, complex64, seed {BATCH_SEED}"),
+           "circuits_per_s": round(BATCH_COUNT / (ms * 1e-3), 1),
+           "ms_per_batch": round(ms, 3),
+           "amp_updates_per_s": round(st["amp_updates"] / (ms * 1e-3), 1),
+           "tile_log2": st["tile_log2"], "reg_log2": st["reg_log2"],
+           "grid": st["grid"], "single_tile_variants": st["single_tile"],
+           "scratch_bytes": st["scratch_bytes"],
+           "host_generate_s": round(t1 - t0, 2),
+           "host_plan_upload_autotune_s": round(t2 - t1, 2),
+           "output_floats": int(b.offsets[-1])}
+    b.free()
+    if per_circuit:
+        circs = []
+        for v in vs:
+            g = [Gate(n, (q,)) for q, lab in v.cut_inputs for n in PROLOGUE[lab]]
+            g += list(v.gates)
+            g += [Gate(n, (q,)) for q, bas in v.cut_outputs
+                  for n in EPILOGUE[bas]]
+            circs.append(qsv.Circuit.from_gates(g))
+        states = {w: qsv.State(w, qsv.QSV_C64,
+                               stream=torch.cuda.current_stream())
+                  for w in sorted({v.width for v in vs})}
+        offs = b.offsets
+        base = out.data_ptr()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for i, v in enumerate(vs):
+            s = states[v.width]
+            s.init_basis(0)
+            s.apply_fused(circs[i])
+            s.probabilities_into(base + 4 * int(offs[i]), False)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        res["per_circuit_s"] = round(t4 - t3, 3)
+        res["per_circuit_circuits_per_s"] = round(BATCH_COUNT / (t4 - t3), 1)
+        res["speedup_vs_per_circuit"] = round((t4 - t3) / (ms * 1e-3), 2)
+        for s in states.values():
+            s.free()
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
 # --------------------------------------------------------------- GPU leg
 
 def main() -> int:
@@ -102,6 +176,10 @@ def main() -> int:
                     help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-leg", type=float, default=None,
                     help=argparse.SUPPRESS)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched cut-variant leg")
+    ap.add_argument("--no-per-circuit", action="store_true",
+                    help="skip the one-call-per-circuit batch baseline")
     a = ap.parse_args()
 
     if a.cpu_leg is not None:
@@ -244,6 +322,11 @@ def main() -> int:
                      "launches": int(sel.size)},
     }
     state.free()
+    del probs
+    torch.cuda.empty_cache()
+    if not a.no_batch:
+        out["batch"] = batch_leg(qsv, torch, np, max(1, a.steps),
+                                 not a.no_per_circuit)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline(a.cpu_budget)
     else:

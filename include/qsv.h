@@ -187,6 +187,12 @@ qsv_status qsv_plan_describe(const qsv_circuit* circ, int32_t n_qubits,
 qsv_status qsv_gate_matrix(const char* name, const double* params,
                            int32_t n_params, double* out, int32_t* k_out);
 
+/* qsv_gate_matrix for `count` gates of one name: params holds count x
+ * n_params values (gate i uses params[i*n_params ...]); out receives count
+ * consecutive 2x2 matrices (8 doubles each). */
+qsv_status qsv_gate_matrices(const char* name, const double* params,
+                             int32_t n_params, size_t count, double* out);
+
 /* ------------------------------------------------------------ reductions */
 
 /* p_i = |a_i|^2 for all 2^n amplitudes into out_dev (caller-owned device
@@ -221,6 +227,77 @@ qsv_status qsv_marginal(qsv_state s, const int32_t* qubits, int32_t m,
  * order.  n_shots <= 2^32.  Waits for the stream. */
 qsv_status qsv_sample(qsv_state s, uint64_t n_shots, uint64_t seed,
                       uint64_t* out_host);
+
+/* ------------------------------------------------- batched cut variants */
+
+/* One subcircuit variant (Section III.A): a width-qubit circuit started in
+ * |0...0>, whose cut-input qubits are first prepared in |0>, |1>, |+> or
+ * |+i> (labels 0..3; the eigenstates of eqs 3.3-3.6, |+i> = S H |0>) and
+ * whose cut-output qubits are finally rotated so that a computational-basis
+ * readout measures I (basis 0: nothing), X (basis 1: H) or Y (basis 2:
+ * S-dagger then H).  The body gates must be one-target dense gates (any
+ * controls) or diagonal gates on at most two targets (or masked phases).
+ * reg_log2 + 2 <= width <= QSV_BATCH_MAX_WIDTH (so width >= 6 at the
+ * default reg_log2 = 4).  All arrays are host memory. */
+#define QSV_BATCH_MAX_WIDTH 24
+typedef struct {
+  int32_t width;
+  qsv_circuit body;
+  int32_t n_inputs;
+  const int32_t* input_qubits;
+  const int32_t* input_labels;
+  int32_t n_outputs;
+  const int32_t* output_qubits;
+  const int32_t* output_bases;
+} qsv_variant;
+
+/* Options of a batch; all-zero (or NULL) selects defaults.
+ *   tile_log2 : tile size for every variant wider than it (default 12 c64,
+ *               11 c128); variants at most this wide run in one tile
+ *   reg_log2  : amplitudes per thread, as log2 (4, or 5 for c64)
+ *   grid      : work-groups of the persistent launch (default 3 per CU)
+ *   autotune  : time (tile_log2, reg_log2) candidates at creation and keep
+ *               the fastest
+ *   use_graph : capture the launch in a hipGraph and replay it
+ *   out_fp64  : probabilities as double (else float) */
+typedef struct {
+  int32_t tile_log2;
+  int32_t reg_log2;
+  int32_t grid;
+  int32_t autotune;
+  int32_t use_graph;
+  int32_t out_fp64;
+} qsv_batch_opts;
+
+typedef struct qsv_batch_s* qsv_batch;
+
+/* Plan count variants of precision prec for one persistent launch on
+ * hip_stream: the variants' programs are uploaded once, the work-groups
+ * take variants longest-first in a fixed order (each variant's result is
+ * independent of the rest of the batch), and every variant's probability
+ * vector is written to a ragged output.  Allocates the program and the
+ * scratch slots of variants wider than one tile. */
+qsv_status qsv_batch_create(const qsv_variant* vars, size_t count,
+                            int32_t prec, const qsv_batch_opts* opts,
+                            void* hip_stream, qsv_batch* out);
+
+/* Ragged output layout: variant i's 2^width probabilities occupy elements
+ * [offsets[i], offsets[i+1]) of the output; offsets holds count + 1. */
+qsv_status qsv_batch_out_offsets(qsv_batch b, uint64_t* offsets);
+
+/* Enqueue the batch (one kernel launch, or one graph replay) writing all
+ * probability vectors into out_dev (caller-owned device memory of
+ * offsets[count] floats or doubles). */
+qsv_status qsv_batch_launch(qsv_batch b, void* out_dev);
+
+/* out[0] variants, out[1] tile passes, out[2] tiles processed, out[3] ops,
+ * out[4] scratch bytes, out[5] tile_log2, out[6] reg_log2, out[7] grid,
+ * out[8] variants run in one tile, out[9] amplitude updates (sum over
+ * variants of 2^width x ops).  n_out <= 10. */
+qsv_status qsv_batch_stats(qsv_batch b, uint64_t* out, int32_t n_out);
+
+/* Release a batch (waits for its stream).  NULL is a no-op. */
+qsv_status qsv_batch_free(qsv_batch b);
 
 /* ---------------------------------------------------- copies and control */
 

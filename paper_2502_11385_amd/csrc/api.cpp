@@ -174,6 +174,13 @@ size_t put(std::vector<char>& buf, const T* data, size_t count) {
 
 }  // namespace
 
+namespace qsv {
+// Error reporting shared with the batch and server front ends.
+qsv_status set_error(qsv_status st, const std::string& msg) {
+  return fail(st, msg);
+}
+}  // namespace qsv
+
 // ======================================================================
 
 extern "C" {
@@ -371,71 +378,9 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
   for (size_t pi = 0; pi < plan.passes.size(); ++pi) {
     const Pass& p = plan.passes[pi];
     if (p.kind == kPassTile) {
-      TilePass tp = {};
-      tp.L = p.L;
-      tp.nseg = int32_t(p.segs.size());
-      tp.seg_begin = int32_t(tsegs.size());
-      int local_of[64];
-      for (int j = 0; j < p.L; ++j) {
-        tp.q[j] = p.q[j];
-        local_of[p.q[j]] = j;
-      }
-      for (const auto& sg : p.segs) {
-        TileSeg ts = {};
-        for (int i = 0; i < po.reg_log2; ++i) ts.reg_bits[i] = sg.reg_bits[i];
-        ts.op_begin = int32_t(tops.size());
-        for (int gi : sg.gates) {
-          const HostGate& g = G[gi];
-          TileOp op = {};
-          for (int j = 0; j < g.c; ++j) {
-            const int q = g.ctl[j];
-            if (p.qubits >> q & 1)
-              op.lctrl |= 1u << local_of[q];
-            else
-              op.gctrl |= uint64_t(1) << q;
-          }
-          const int d = 1 << g.k;
-          if (!g.diagonal) {
-            op.kind = kOpDense1;
-            const int lb = local_of[g.t[0]];
-            op.reg = -1;
-            for (int i = 0; i < po.reg_log2; ++i)
-              if (sg.reg_bits[i] == lb) op.reg = i;
-            if (op.reg < 0)
-              return fail(QSV_ERR_DEVICE, "internal planner error: target "
-                                          "not in a register bit");
-            for (int e = 0; e < 8; ++e) op.m[e] = g.m[e];
-          } else if (g.masked_phase) {
-            op.kind = kOpPhase;
-            for (int j = 0; j < g.k; ++j) {
-              const int q = g.t[j];
-              if (p.qubits >> q & 1)
-                op.lctrl |= 1u << local_of[q];
-              else
-                op.gctrl |= uint64_t(1) << q;
-            }
-            op.m[0] = g.m[2 * ((d - 1) * d + (d - 1))];
-            op.m[1] = g.m[2 * ((d - 1) * d + (d - 1)) + 1];
-          } else {
-            op.kind = kOpDiag;
-            op.dk = g.k;
-            int* db[2] = {&op.dbit0, &op.dbit1};
-            for (int j = 0; j < g.k; ++j) {
-              const int q = g.t[j];
-              *db[j] = (p.qubits >> q & 1) ? local_of[q] : -1 - q;
-            }
-            for (int r = 0; r < d; ++r) {
-              op.m[2 * r] = g.m[2 * (r * d + r)];
-              op.m[2 * r + 1] = g.m[2 * (r * d + r) + 1];
-            }
-          }
-          for (int e = 0; e < 8; ++e) op.mf[e] = float(op.m[e]);
-          tops.push_back(op);
-        }
-        ts.op_end = int32_t(tops.size());
-        tsegs.push_back(ts);
-      }
-      tpasses.push_back(tp);
+      std::string err = emit_tile_pass(p, G, po.reg_log2, &tpasses, &tsegs,
+                                       &tops);
+      if (!err.empty()) return fail(QSV_ERR_DEVICE, err);
     } else if (p.kind == kPassPlain) {
       const HostGate& g = G[p.gates[0]];
       if (!g.diagonal && g.k >= 3) {
@@ -671,6 +616,21 @@ qsv_status qsv_gate_matrix(const char* name, const double* params,
   }
   std::memcpy(out, m, sizeof m);
   *k_out = 1;
+  return QSV_OK;
+}
+
+qsv_status qsv_gate_matrices(const char* name, const double* params,
+                             int32_t n_params, size_t count, double* out) {
+  if (!out || (count && n_params > 0 && !params))
+    return fail(QSV_ERR_INVALID_ARG, "null argument");
+  if (n_params < 0) return fail(QSV_ERR_INVALID_ARG, "negative n_params");
+  int32_t k = 0;
+  for (size_t i = 0; i < count; ++i) {
+    qsv_status st = qsv_gate_matrix(
+        name, n_params ? params + i * size_t(n_params) : nullptr, n_params,
+        out + 8 * i, &k);
+    if (st != QSV_OK) return st;
+  }
   return QSV_OK;
 }
 

@@ -230,6 +230,77 @@ static void plan_fused(const std::vector<HostGate>& G, int n, int b,
   }
 }
 
+std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
+                           int RB, std::vector<TilePass>* tpasses,
+                           std::vector<TileSeg>* tsegs,
+                           std::vector<TileOp>* tops) {
+  TilePass tp = {};
+  tp.L = p.L;
+  tp.nseg = int32_t(p.segs.size());
+  tp.seg_begin = int32_t(tsegs->size());
+  int local_of[64];
+  for (int j = 0; j < p.L; ++j) {
+    tp.q[j] = p.q[j];
+    local_of[p.q[j]] = j;
+  }
+  for (const auto& sg : p.segs) {
+    TileSeg ts = {};
+    for (int i = 0; i < RB; ++i) ts.reg_bits[i] = sg.reg_bits[i];
+    ts.op_begin = int32_t(tops->size());
+    for (int gi : sg.gates) {
+      const HostGate& g = G[gi];
+      TileOp op = {};
+      for (int j = 0; j < g.c; ++j) {
+        const int q = g.ctl[j];
+        if (p.qubits >> q & 1)
+          op.lctrl |= 1u << local_of[q];
+        else
+          op.gctrl |= uint64_t(1) << q;
+      }
+      const int d = 1 << g.k;
+      if (!g.diagonal) {
+        op.kind = kOpDense1;
+        const int lb = local_of[g.t[0]];
+        op.reg = -1;
+        for (int i = 0; i < RB; ++i)
+          if (sg.reg_bits[i] == lb) op.reg = i;
+        if (op.reg < 0)
+          return "internal planner error: target not in a register bit";
+        for (int e = 0; e < 8; ++e) op.m[e] = g.m[e];
+      } else if (g.masked_phase) {
+        op.kind = kOpPhase;
+        for (int j = 0; j < g.k; ++j) {
+          const int q = g.t[j];
+          if (p.qubits >> q & 1)
+            op.lctrl |= 1u << local_of[q];
+          else
+            op.gctrl |= uint64_t(1) << q;
+        }
+        op.m[0] = g.m[2 * ((d - 1) * d + (d - 1))];
+        op.m[1] = g.m[2 * ((d - 1) * d + (d - 1)) + 1];
+      } else {
+        op.kind = kOpDiag;
+        op.dk = g.k;
+        int* db[2] = {&op.dbit0, &op.dbit1};
+        for (int j = 0; j < g.k; ++j) {
+          const int q = g.t[j];
+          *db[j] = (p.qubits >> q & 1) ? local_of[q] : -1 - q;
+        }
+        for (int r = 0; r < d; ++r) {
+          op.m[2 * r] = g.m[2 * (r * d + r)];
+          op.m[2 * r + 1] = g.m[2 * (r * d + r) + 1];
+        }
+      }
+      for (int e = 0; e < 8; ++e) op.mf[e] = float(op.m[e]);
+      tops->push_back(op);
+    }
+    ts.op_end = int32_t(tops->size());
+    tsegs->push_back(ts);
+  }
+  tpasses->push_back(tp);
+  return "";
+}
+
 void make_plan(const std::vector<HostGate>& G, int n, int b,
                const PlanOptions& o, Plan* plan) {
   *plan = Plan();

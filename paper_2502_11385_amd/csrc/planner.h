@@ -71,6 +71,13 @@ std::string make_gate(int n, int k, int c, const int32_t* qubits,
 void make_plan(const std::vector<HostGate>& gates, int n, int bytes_per_amp,
                const PlanOptions& opt, Plan* plan);
 
+// Append the device records of one tile pass (its TilePass, segments and
+// ops; segment and op indices are global into the output vectors).
+std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
+                           int reg_log2, std::vector<TilePass>* passes,
+                           std::vector<TileSeg>* segs,
+                           std::vector<TileOp>* ops);
+
 // Algorithmic bytes of applying gate g as a plain per-gate kernel.
 uint64_t plain_gate_bytes(const HostGate& g, int n, int bytes_per_amp);
 

@@ -84,4 +84,14 @@ struct alignas(16) FusedBlock {
   int32_t q[8];
 };
 
+// One variant of a batch: its width, its tile passes (all its gates run in
+// tile passes) and where its 2^w probabilities go in the ragged output.
+struct alignas(16) BatchCircuit {
+  int32_t w;
+  int32_t n_passes;
+  int32_t pass_begin;
+  int32_t pad;
+  uint64_t out_offset;
+};
+
 }  // namespace qsv

@@ -46,6 +46,8 @@ EXPORTED = [
     "qsv_marginal", "qsv_sample", "qsv_get_amplitudes", "qsv_set_amplitudes",
     "qsv_info", "qsv_sync", "qsv_last_error", "qsv_version",
     "qsv_set_profiling", "qsv_pass_times",
+    "qsv_batch_create", "qsv_batch_out_offsets", "qsv_batch_launch",
+    "qsv_batch_stats", "qsv_batch_free", "qsv_gate_matrices",
 ]
 
 
@@ -69,6 +71,22 @@ class qsv_fuse_opts(C.Structure):
                 ("reg_log2", C.c_int32)]
 
 
+class qsv_variant(C.Structure):
+    _fields_ = [("width", C.c_int32), ("body", qsv_circuit),
+                ("n_inputs", C.c_int32),
+                ("input_qubits", C.POINTER(C.c_int32)),
+                ("input_labels", C.POINTER(C.c_int32)),
+                ("n_outputs", C.c_int32),
+                ("output_qubits", C.POINTER(C.c_int32)),
+                ("output_bases", C.POINTER(C.c_int32))]
+
+
+class qsv_batch_opts(C.Structure):
+    _fields_ = [("tile_log2", C.c_int32), ("reg_log2", C.c_int32),
+                ("grid", C.c_int32), ("autotune", C.c_int32),
+                ("use_graph", C.c_int32), ("out_fp64", C.c_int32)]
+
+
 _p = C.c_void_p
 _i32 = C.c_int32
 _u64 = C.c_uint64
@@ -88,6 +106,7 @@ _SIGS = {
                           C.POINTER(qsv_fuse_opts), _pi32, _pi32, _pi32,
                           _pu64, _pi32],
     "qsv_gate_matrix": [C.c_char_p, _pd, _i32, _pd, _pi32],
+    "qsv_gate_matrices": [C.c_char_p, _pd, _i32, C.c_size_t, _pd],
     "qsv_probabilities": [_p, _p, _i32],
     "qsv_norm": [_p, _pd],
     "qsv_renormalize": [_p, _pd],
@@ -98,6 +117,12 @@ _SIGS = {
     "qsv_info": [_p, C.POINTER(_p), _pi32, _pi32],
     "qsv_sync": [_p],
     "qsv_set_profiling": [_p, _i32],
+    "qsv_batch_create": [C.POINTER(qsv_variant), C.c_size_t, _i32,
+                         C.POINTER(qsv_batch_opts), _p, C.POINTER(_p)],
+    "qsv_batch_out_offsets": [_p, _pu64],
+    "qsv_batch_launch": [_p, _p],
+    "qsv_batch_stats": [_p, _pu64, _i32],
+    "qsv_batch_free": [_p],
     "qsv_pass_times": [_p, C.POINTER(C.c_float), _pi32, _i32, _pi32],
 }
 for _name, _args in _SIGS.items():
@@ -144,6 +169,17 @@ def gate_matrix(name: str, params: Sequence[float] = ()) -> np.ndarray:
     return (out[0::2] + 1j * out[1::2]).reshape(2, 2)
 
 
+def gate_matrices(name: str, params) -> np.ndarray:
+    """Standard 2x2 matrices of one gate name for many parameter tuples."""
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    count = p.shape[0]
+    npar = p.shape[1] if p.ndim == 2 else 0
+    out = np.zeros((count, 8), dtype=np.float64)
+    _check(_lib.qsv_gate_matrices(name.encode(), _ptr(p, C.c_double),
+                                  npar, count, _ptr(out, C.c_double)))
+    return (out[:, 0::2] + 1j * out[:, 1::2]).reshape(count, 2, 2)
+
+
 class Circuit:
     """A gate list flattened into the arrays of ``qsv_circuit``."""
 
@@ -184,9 +220,23 @@ class Circuit:
 
     @classmethod
     def from_gates(cls, gates: Iterable) -> "Circuit":
+        gates = list(gates)
+        # parametrised gates: one library call per gate name
+        mats = {}
+        for name in {g.name for g in gates if g.params}:
+            ps = [g.params for g in gates if g.name == name]
+            base = "p" if name == "cp" else name
+            mats[name] = iter(gate_matrices(base, ps))
         c = cls()
         for g in gates:
-            c.add_named(g.name, g.qubits, g.params)
+            if g.params:
+                m = next(mats[g.name])
+                if g.name == "cp":
+                    c.add([g.qubits[1]], m, [g.qubits[0]])
+                else:
+                    c.add([g.qubits[0]], m)
+            else:
+                c.add_named(g.name, g.qubits, g.params)
         return c
 
     def __len__(self):
@@ -369,3 +419,81 @@ class State:
 
     def sync(self):
         _check(_lib.qsv_sync(self._h))
+
+
+# ---------------------------------------------------------------- batches
+
+INIT_CODE = {"0": 0, "1": 1, "+": 2, "+i": 3}
+BASIS_CODE = {"I": 0, "X": 1, "Y": 2}
+
+
+class Batch:
+    """A planned batch of subcircuit variants for one persistent launch.
+
+    ``variants`` are ``circuits.BatchCircuit`` records (width, gates,
+    cut_inputs [(qubit, label)], cut_outputs [(qubit, basis)])."""
+
+    def __init__(self, variants, prec: int = QSV_C64, stream=None,
+                 tile_log2: int = 0, reg_log2: int = 0, grid: int = 0,
+                 autotune: bool = False, use_graph: bool = False,
+                 out_fp64: bool = False):
+        self.count = len(variants)
+        self.prec = prec
+        self.out_fp64 = out_fp64
+        keep = []
+        arr = (qsv_variant * self.count)()
+        for i, v in enumerate(variants):
+            circ = Circuit.from_gates(v.gates)
+            iq = np.asarray([q for q, _ in v.cut_inputs], np.int32)
+            il = np.asarray([INIT_CODE[l] for _, l in v.cut_inputs], np.int32)
+            oq = np.asarray([q for q, _ in v.cut_outputs], np.int32)
+            ob = np.asarray([BASIS_CODE[b] for _, b in v.cut_outputs],
+                            np.int32)
+            keep += [circ, iq, il, oq, ob]
+            arr[i].width = v.width
+            arr[i].body = circ.struct()
+            arr[i].n_inputs = len(iq)
+            arr[i].input_qubits = _ptr(iq, C.c_int32)
+            arr[i].input_labels = _ptr(il, C.c_int32)
+            arr[i].n_outputs = len(oq)
+            arr[i].output_qubits = _ptr(oq, C.c_int32)
+            arr[i].output_bases = _ptr(ob, C.c_int32)
+        opts = qsv_batch_opts(tile_log2, reg_log2, grid, int(autotune),
+                              int(use_graph), int(out_fp64))
+        self._h = C.c_void_p()
+        _check(_lib.qsv_batch_create(arr, self.count, prec, C.byref(opts),
+                                     _stream_handle(stream), C.byref(self._h)))
+        del keep
+        self.offsets = np.zeros(self.count + 1, np.uint64)
+        _check(_lib.qsv_batch_out_offsets(self._h,
+                                          _ptr(self.offsets, C.c_uint64)))
+
+    def output(self):
+        """A device buffer (torch tensor) for the ragged output."""
+        import torch
+        dt = torch.float64 if self.out_fp64 else torch.float32
+        return torch.empty(int(self.offsets[-1]), dtype=dt, device="cuda")
+
+    def launch(self, out) -> None:
+        ptr = out.data_ptr() if hasattr(out, "data_ptr") else int(out)
+        _check(_lib.qsv_batch_launch(self._h, ptr))
+
+    def stats(self) -> dict:
+        out = np.zeros(10, np.uint64)
+        _check(_lib.qsv_batch_stats(self._h, _ptr(out, C.c_uint64), 10))
+        keys = ("variants", "passes", "tiles", "ops", "scratch_bytes",
+                "tile_log2", "reg_log2", "grid", "single_tile",
+                "amp_updates")
+        return {k: int(v) for k, v in zip(keys, out)}
+
+    def free(self):
+        if self._h:
+            _check(_lib.qsv_batch_free(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._h:
+                _lib.qsv_batch_free(self._h)
+        except Exception:
+            pass

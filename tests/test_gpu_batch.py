@@ -1,0 +1,126 @@
+"""Batched ragged cut variants on the GPU against the oracle's own variant
+construction (prologue, body, epilogue, probabilities)."""
+import numpy as np
+import pytest
+
+import oracle
+from circuits import BatchCircuit, Gate, batch_variants
+
+torch = pytest.importorskip("torch")
+from paper_2502_11385_amd import qsv  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+C64, C128 = qsv.QSV_C64, qsv.QSV_C128
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _check(out, offs, variants, prec):
+    got = out.cpu().numpy()
+    worst = 0.0
+    for i, v in enumerate(variants):
+        p = got[int(offs[i]):int(offs[i + 1])].astype(np.float64)
+        want = oracle.variant_probabilities(v)
+        err = float(np.max(np.abs(p - want)))
+        worst = max(worst, err)
+        if prec == C64:
+            assert err <= 2e-6, (i, v.width, err)
+            assert 0.5 * np.sum(np.abs(p - want)) <= 1e-4
+        else:
+            assert err <= 1e-12, (i, v.width, err)
+    return worst
+
+
+SMALL = dict(count=40, seed=7, wmin=6, wmax=14, dmin=2, dmax=12)
+
+
+@pytest.mark.parametrize("prec", [C64, C128])
+@pytest.mark.parametrize("cfg", [dict(), dict(tile_log2=10),
+                                 dict(tile_log2=9), dict(reg_log2=5)])
+def test_batch_parity_small(prec, cfg):
+    if prec == C128 and cfg.get("reg_log2") == 5:
+        pytest.skip("reg_log2 = 5 is complex64 only")
+    small = dict(SMALL)
+    if cfg.get("reg_log2") == 5:
+        small["wmin"] = 7          # width >= reg_log2 + 2
+    vs = batch_variants(**small)
+    b = qsv.Batch(vs, prec=prec, out_fp64=(prec == C128), **cfg)
+    out = b.output()
+    b.launch(out)
+    torch.cuda.synchronize()
+    _check(out, b.offsets, vs, prec)
+    st = b.stats()
+    assert st["variants"] == len(vs)
+    b.free()
+
+
+@pytest.mark.parametrize("prec", [C64, C128])
+def test_batch_parity_wide_multipass(prec):
+    vs = batch_variants(count=5, seed=11, wmin=15, wmax=19, dmin=2, dmax=5)
+    b = qsv.Batch(vs, prec=prec, out_fp64=(prec == C128), tile_log2=10)
+    assert b.stats()["scratch_bytes"] > 0
+    out = b.output()
+    b.launch(out)
+    torch.cuda.synchronize()
+    _check(out, b.offsets, vs, prec)
+
+
+def test_alone_equals_in_batch_bitwise():
+    vs = batch_variants(count=30, seed=3, wmin=8, wmax=13, dmin=2, dmax=10)
+    big = qsv.Batch(vs, prec=C64)
+    out = big.output()
+    big.launch(out)
+    torch.cuda.synchronize()
+    allp = out.cpu().numpy()
+    for i in (0, 7, 29):
+        one = qsv.Batch([vs[i]], prec=C64)
+        o1 = one.output()
+        one.launch(o1)
+        torch.cuda.synchronize()
+        sl = allp[int(big.offsets[i]):int(big.offsets[i + 1])]
+        assert np.array_equal(o1.cpu().numpy(), sl)
+
+
+def test_graph_replay_matches_direct():
+    vs = batch_variants(count=24, seed=5, wmin=8, wmax=14, dmin=2, dmax=8)
+    direct = qsv.Batch(vs, prec=C64)
+    od = direct.output()
+    direct.launch(od)
+    torch.cuda.synchronize()
+    ref = od.cpu().numpy()
+    g = qsv.Batch(vs, prec=C64, use_graph=True)
+    og = g.output()
+    for rep in range(3):
+        og.zero_()
+        torch.cuda.synchronize()
+        g.launch(og)
+        torch.cuda.synchronize()
+        x = torch.ones(1000, device="cuda").sum().item()   # eager work between
+        assert x == 1000.0
+        assert np.array_equal(og.cpu().numpy(), ref), rep
+
+
+def test_autotune_picks_a_valid_config():
+    vs = batch_variants(count=64, seed=9, wmin=10, wmax=14, dmin=2, dmax=8)
+    b = qsv.Batch(vs, prec=C64, autotune=True)
+    st = b.stats()
+    assert st["tile_log2"] in (10, 11, 12) and st["reg_log2"] in (4, 5)
+    out = b.output()
+    b.launch(out)
+    torch.cuda.synchronize()
+    _check(out, b.offsets, vs[:16], C64)
+
+
+def test_empty_body_variant():
+    vs = [BatchCircuit(8, 1, [], [(0, "+"), (3, "1")], [(3, "X")]),
+          BatchCircuit(9, 1, [Gate("h", (1,))], [], [])]
+    b = qsv.Batch(vs, prec=C128, out_fp64=True)
+    out = b.output()
+    b.launch(out)
+    torch.cuda.synchronize()
+    _check(out, b.offsets, vs, C128)
