@@ -157,6 +157,82 @@ def batch_leg(qsv, torch, np, steps: int, per_circuit: bool) -> dict:
     return res
 
 
+# --------------------------------------------------------------- serve leg
+
+def _replay(qsv, reqs, circs, arrivals, serial: bool) -> dict:
+    """Submit each request at its arrival time (seconds from start) to a
+    fresh server and wait for all; latency = done - submit."""
+    import threading
+    import numpy as np
+    srv = qsv.Server(serial=serial)
+    tickets = [None] * len(reqs)
+    infos = [None] * len(reqs)
+    ready = threading.Semaphore(0)
+
+    def waiter():
+        for i in range(len(reqs)):
+            ready.acquire()
+            _, info = srv.wait(tickets[i], copy=False)
+            srv.release(tickets[i])
+            infos[i] = info
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for i, r in enumerate(reqs):
+        dt = arrivals[i] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets[i] = srv.submit(r.width, circs[i],
+                                qsv.QSV_C64 if r.precision == "c64"
+                                else qsv.QSV_C128,
+                                shots=r.shots if r.want_samples else 0,
+                                seed=r.seed)
+        ready.release()
+    th.join()
+    st = srv.stats()
+    srv.close()
+    lat = np.array([x["t_done"] - x["t_submit"] for x in infos])
+    span = max(x["t_done"] for x in infos) - min(x["t_submit"] for x in infos)
+    return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "circuits_per_s": round(len(reqs) / span, 2),
+            "batch_launches": st["batch_launches"],
+            "single_launches": st["single_launches"],
+            "max_groups_in_flight": st["max_groups_in_flight"],
+            "peak_reserved_GB": round(st["peak_reserved_bytes"] / 1e9, 3)}
+
+
+def serve_leg(qsv, n: int) -> dict:
+    """Poisson request stream (widths 8..28, depths 10..100, c64 80 %,
+    probability vector or 1e4 samples): serial per-request execution
+    against continuous batching, on the same seeded trace replayed at
+    0.8 and 2 times the serial service rate."""
+    import numpy as np
+    from circuits import layered_circuit, serve_trace
+    reqs = serve_trace(n + 100, rate_per_s=1.0, seed=5)
+    circs = [qsv.Circuit.from_gates(layered_circuit(r.width, r.depth, r.seed))
+             for r in reqs]
+    # calibrate the serial service rate on 100 warm-up requests
+    warm = _replay(qsv, reqs[:100], circs[:100], [0.0] * 100, True)
+    mu = warm["circuits_per_s"]
+    base = np.array([r.arrival_s for r in reqs[100:]])
+    base = base - base[0]
+    out = {"workload": (f"{n} requests, widths 8..28, depths 10..100, "
+                        "c64 80% / c128 20%, probabilities or 1e4 samples, "
+                        "Poisson arrivals (seed 5), budget 256 GB"),
+           "serial_rate_per_s": mu}
+    for f in (0.8, 2.0):
+        lam = f * mu
+        arr = base / lam            # the unit-rate trace scaled to lam
+        key = f"lambda_{f}x"
+        out[key] = {"rate_per_s": round(lam, 2),
+                    "serial": _replay(qsv, reqs[100:], circs[100:], arr, True),
+                    "continuous": _replay(qsv, reqs[100:], circs[100:], arr,
+                                          False)}
+    return out
+
+
 # --------------------------------------------------------------- GPU leg
 
 def main() -> int:
@@ -180,6 +256,10 @@ def main() -> int:
                     help="skip the batched cut-variant leg")
     ap.add_argument("--no-per-circuit", action="store_true",
                     help="skip the one-call-per-circuit batch baseline")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the request-serving leg")
+    ap.add_argument("--serve-n", type=int, default=300,
+                    help="requests per serving run (after 100 warm-up)")
     a = ap.parse_args()
 
     if a.cpu_leg is not None:
@@ -327,6 +407,8 @@ def main() -> int:
     if not a.no_batch:
         out["batch"] = batch_leg(qsv, torch, np, max(1, a.steps),
                                  not a.no_per_circuit)
+    if not a.no_serve:
+        out["serve"] = serve_leg(qsv, a.serve_n)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline(a.cpu_budget)
     else:

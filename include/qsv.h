@@ -299,6 +299,86 @@ qsv_status qsv_batch_stats(qsv_batch b, uint64_t* out, int32_t n_out);
 /* Release a batch (waits for its stream).  NULL is a no-op. */
 qsv_status qsv_batch_free(qsv_batch b);
 
+/* --------------------------------------------------------------- serving */
+
+/* A request server: requests (circuits of different widths, depths and
+ * precisions) are submitted as they arrive; a scheduler thread admits them
+ * first-come first-served while the HBM they need (state 2^w x 8 or 16
+ * bytes plus output) fits the budget, the way the evaluator sizes its
+ * worker pool by the memory each worker needs (Section IV.A).  Admitted
+ * requests of width <= small_width whose gates fit tiles are packed into
+ * batch slots (one persistent launch per group); wider ones run on their
+ * own state.  Groups run on up to n_streams streams at once, so work
+ * admitted while other work is on the GPU overlaps it (continuous
+ * batching).  The path and kernels a request takes depend only on the
+ * request, so its result is the same alone or in any mix.
+ *   budget_bytes : admission budget (0 = 256e9)
+ *   max_batch    : most requests per batch launch (0 = 256)
+ *   small_width  : widest request packed into batch slots (0 = 20)
+ *   n_streams    : concurrent streams (0 = 4)
+ *   serial       : 1 = one request at a time, nothing overlaps (baseline) */
+typedef struct {
+  uint64_t budget_bytes;
+  int32_t max_batch;
+  int32_t small_width;
+  int32_t n_streams;
+  int32_t serial;
+} qsv_server_opts;
+
+/* One request: the circuit runs on |0...0> of `width` qubits; the output
+ * is the probability vector (float for c64, double for c128) or `shots`
+ * samples drawn as in qsv_sample with `seed`. */
+typedef struct {
+  int32_t width;
+  int32_t prec;
+  qsv_circuit body;
+  int32_t want_samples;
+  uint64_t shots;
+  uint64_t seed;
+} qsv_request;
+
+/* A finished request.  data points to host memory owned by the server
+ * until qsv_server_release: n_out floats/doubles (probabilities) or n_out
+ * uint64 samples.  Times are seconds on qsv_clock(). */
+typedef struct {
+  int32_t status;
+  int32_t width;
+  int32_t prec;
+  int32_t is_samples;
+  int32_t batched;
+  int32_t pad;
+  uint64_t n_out;
+  const void* data;
+  double t_submit, t_admit, t_start, t_done;
+} qsv_result;
+
+typedef struct qsv_server_s* qsv_server;
+
+/* Create a server (no device work until the first request runs). */
+qsv_status qsv_server_create(const qsv_server_opts* opts, qsv_server* out);
+
+/* Validate and enqueue a request (inputs are copied); returns its ticket.
+ * QSV_ERR_BUDGET if the request alone exceeds the budget. */
+qsv_status qsv_server_submit(qsv_server s, const qsv_request* req,
+                             uint64_t* ticket);
+
+/* Block until the ticket's request has finished and describe its result. */
+qsv_status qsv_server_wait(qsv_server s, uint64_t ticket, qsv_result* out);
+
+/* Free the ticket's result buffers. */
+qsv_status qsv_server_release(qsv_server s, uint64_t ticket);
+
+/* out[0] submitted, out[1] completed, out[2] batch launches, out[3] single
+ * launches, out[4] peak reserved bytes, out[5] most groups in flight at
+ * once, out[6] rejected.  n_out <= 7. */
+qsv_status qsv_server_stats(qsv_server s, uint64_t* out, int32_t n_out);
+
+/* Finish queued work, stop the scheduler and free everything. */
+qsv_status qsv_server_destroy(qsv_server s);
+
+/* The library's steady clock, in seconds. */
+double qsv_clock(void);
+
 /* ---------------------------------------------------- copies and control */
 
 /* Copy all amplitudes to / from host memory (2^n interleaved pairs of the

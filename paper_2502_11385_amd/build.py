@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build", "qsv")
 LIB = os.path.join(HERE, "libqsv.so")
 
-SOURCES = ["api.cpp", "planner.cpp", "batch.cpp", "k_gate.hip",
+SOURCES = ["api.cpp", "planner.cpp", "batch.cpp", "server.cpp", "k_gate.hip",
            "k_tile.hip", "k_reduce.hip", "k_fused.hip", "k_batch.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -50,7 +50,8 @@ def build(verbose: bool = True) -> str:
     with ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + \
+        objs + ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

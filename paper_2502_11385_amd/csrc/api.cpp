@@ -179,6 +179,18 @@ namespace qsv {
 qsv_status set_error(qsv_status st, const std::string& msg) {
   return fail(st, msg);
 }
+
+// Draw shots into a device buffer without waiting (used by the server).
+qsv_status state_sample_async(qsv_state s, uint64_t shots, uint64_t seed,
+                              uint64_t* dev_out) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if ((st = ensure_scratch(s, sample_scratch_bytes(s->n, 0))) != QSV_OK)
+    return st;
+  QSV_HIP(s, launch_sample(s->prec, s->amp, s->n, shots, seed, s->scratch,
+                           dev_out, s->stream));
+  return QSV_OK;
+}
 }  // namespace qsv
 
 // ======================================================================

@@ -9,20 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "device_common.h"
-#include "planner.h"
-#include "program.h"
-#include "qsv.h"
-
-namespace qsv {
-qsv_status set_error(qsv_status st, const std::string& msg);
-hipError_t launch_batch(int prec, int out_fp64, int rb, const BatchCircuit* circs,
-                        const int32_t* order, int32_t count,
-                        const TilePass* passes, const TileSeg* segs,
-                        const TileOp* ops, void* out, void* scratch,
-                        uint64_t slot_amps, int L, int grid,
-                        hipStream_t stream);
-}  // namespace qsv
+#include "batch_internal.h"
 
 using namespace qsv;
 
@@ -34,17 +21,6 @@ const double kX[8] = {0, 0, 1, 0, 1, 0, 0, 0};
 const double kH[8] = {kR2, 0, kR2, 0, kR2, 0, -kR2, 0};
 const double kS[8] = {1, 0, 0, 0, 0, 0, 0, 1};
 const double kSdg[8] = {1, 0, 0, 0, 0, 0, 0, -1};
-
-struct HostProgram {
-  std::vector<BatchCircuit> circs;
-  std::vector<int32_t> order;
-  std::vector<TilePass> passes;
-  std::vector<TileSeg> segs;
-  std::vector<TileOp> ops;
-  std::vector<uint64_t> out_offsets;
-  uint64_t slot_amps = 0;
-  uint64_t tiles = 0, amp_updates = 0, single_tile = 0;
-};
 
 std::string variant_gates(const qsv_variant& v, std::vector<HostGate>* G) {
   const int w = v.width;
@@ -104,7 +80,7 @@ std::string variant_gates(const qsv_variant& v, std::vector<HostGate>* G) {
 std::string build_program(const qsv_variant* vars, size_t count, int b,
                           int L, int RB, HostProgram* hp) {
   *hp = HostProgram();
-  hp->out_offsets.assign(count + 1, 0);
+  hp->out_offsets.assign(1, 0);
   std::vector<double> cost(count);
   std::vector<HostGate> G;
   for (size_t i = 0; i < count; ++i) {
@@ -117,30 +93,48 @@ std::string build_program(const qsv_variant* vars, size_t count, int b,
       return "variant " + std::to_string(i) + ": bad cut lists";
     std::string e = variant_gates(v, &G);
     if (!e.empty()) return "variant " + std::to_string(i) + ": " + e;
+    e = append_variant(v.width, G, b, L, RB, hp, &cost[i]);
+    if (!e.empty()) return "variant " + std::to_string(i) + ": " + e;
+  }
+  hp->order.resize(count);
+  std::iota(hp->order.begin(), hp->order.end(), 0);
+  std::stable_sort(hp->order.begin(), hp->order.end(),
+                   [&](int a, int c) { return cost[a] > cost[c]; });
+  return "";
+}
+
+}  // namespace
+
+namespace qsv {
+
+std::string append_variant(int w, const std::vector<HostGate>& G, int b,
+                           int L, int RB, HostProgram* hp, double* cost) {
+  const size_t i = hp->circs.size();
+  std::string e;
+  {
     PlanOptions po;
     po.strategy = 2;
-    po.tile_log2 = std::min(L, v.width);
+    po.tile_log2 = std::min(L, w);
     po.low_qubits = std::min(b == 8 ? 5 : 4, po.tile_log2 - 1);
     po.reg_log2 = RB;
     Plan plan;
-    make_plan(G, v.width, b, po, &plan);
+    make_plan(G, w, b, po, &plan);
     BatchCircuit bc = {};
-    bc.w = v.width;
+    bc.w = w;
     bc.pass_begin = int32_t(hp->passes.size());
     for (const Pass& p : plan.passes) {
       if (p.kind != kPassTile)
-        return "variant " + std::to_string(i) +
-               ": gate not supported in batched tiles (dense k >= 2)";
+        return "gate not supported in batched tiles (dense k >= 2)";
       e = emit_tile_pass(p, G, RB, &hp->passes, &hp->segs, &hp->ops);
       if (!e.empty()) return e;
-      hp->tiles += uint64_t(1) << (v.width - p.L);
+      hp->tiles += uint64_t(1) << (w - p.L);
     }
     bc.n_passes = int32_t(hp->passes.size()) - bc.pass_begin;
     if (bc.n_passes == 0) {
       // an empty variant still needs one pass to write |0...0>'s vector
       Pass p;
       p.kind = kPassTile;
-      p.L = std::min(L, v.width);
+      p.L = std::min(L, w);
       for (int q = 0; q < p.L; ++q) {
         p.q[q] = q;
         p.qubits |= uint64_t(1) << q;
@@ -150,25 +144,27 @@ std::string build_program(const qsv_variant* vars, size_t count, int b,
       p.segs.push_back(sg);
       e = emit_tile_pass(p, G, RB, &hp->passes, &hp->segs, &hp->ops);
       if (!e.empty()) return e;
-      hp->tiles += uint64_t(1) << (v.width - p.L);
+      hp->tiles += uint64_t(1) << (w - p.L);
       bc.n_passes = 1;
     }
+    if (hp->out_offsets.empty()) hp->out_offsets.push_back(0);
     bc.out_offset = hp->out_offsets[i];
-    hp->out_offsets[i + 1] = hp->out_offsets[i] + (uint64_t(1) << v.width);
+    hp->out_offsets.push_back(hp->out_offsets[i] + (uint64_t(1) << w));
     if (bc.n_passes > 1)
-      hp->slot_amps = std::max(hp->slot_amps, uint64_t(1) << v.width);
+      hp->slot_amps = std::max(hp->slot_amps, uint64_t(1) << w);
     else
       hp->single_tile++;
-    hp->amp_updates += (uint64_t(1) << v.width) * G.size();
-    cost[i] = double(uint64_t(1) << v.width) * (double(G.size()) + 4.0 * bc.n_passes);
+    hp->amp_updates += (uint64_t(1) << w) * G.size();
+    if (cost)
+      *cost = double(uint64_t(1) << w) * (double(G.size()) + 4.0 * bc.n_passes);
     hp->circs.push_back(bc);
   }
-  hp->order.resize(count);
-  std::iota(hp->order.begin(), hp->order.end(), 0);
-  std::stable_sort(hp->order.begin(), hp->order.end(),
-                   [&](int a, int c) { return cost[a] > cost[c]; });
   return "";
 }
+
+}  // namespace qsv
+
+namespace {
 
 template <class T>
 size_t put(std::vector<char>& buf, const std::vector<T>& v) {

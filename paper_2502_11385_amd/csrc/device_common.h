@@ -107,5 +107,9 @@ size_t sample_scratch_bytes(int n, uint64_t shots);
 hipError_t launch_sample(int prec, const void* amp, int n, uint64_t shots,
                          uint64_t seed, void* scratch, uint64_t* out_dev,
                          hipStream_t stream);
+// The same draws from a stored probability vector (float or double).
+hipError_t launch_sample_probs(int fp64, const void* probs, int n,
+                               uint64_t shots, uint64_t seed, void* scratch,
+                               uint64_t* out_dev, hipStream_t stream);
 
 }  // namespace qsv

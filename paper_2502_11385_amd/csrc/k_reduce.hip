@@ -268,10 +268,23 @@ __device__ __forceinline__ double wave_incl_scan(double v) {
   return v;
 }
 
+// Probability of element i of the sampled vector: an amplitude's |a|^2, or a
+// stored probability.
 template <typename T>
+struct FromAmps {
+  using in_t = typename CxT<T>::type;
+  static __device__ __forceinline__ double p(in_t v) { return prob_of(v); }
+};
+template <typename P>
+struct FromProbs {
+  using in_t = P;
+  static __device__ __forceinline__ double p(P v) { return double(v); }
+};
+
+template <class Acc>
 __global__ void __launch_bounds__(256)
-    sample_blocksum_kernel(const typename CxT<T>::type* __restrict__ a,
-                           int B, uint64_t nblocks, double* __restrict__ S) {
+    sample_blocksum_kernel(const typename Acc::in_t* __restrict__ a, int B,
+                           uint64_t nblocks, double* __restrict__ S) {
   const uint64_t w = uint64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (w >= nblocks) return;  // whole waves exit together
@@ -280,7 +293,7 @@ __global__ void __launch_bounds__(256)
   double loc = 0;
   if (lane < lanes)
     for (int e = 0; e < E; ++e)
-      loc += prob_of(a[(w << B) + uint64_t(lane) * E + e]);
+      loc += Acc::p(a[(w << B) + uint64_t(lane) * E + e]);
   const double incl = wave_incl_scan(loc);
   if (lane == 63) S[w] = incl;
 }
@@ -349,9 +362,9 @@ static void scan_inclusive(double* d, uint64_t count, double* scratch,
   scan_add_kernel<<<unsigned(blocks), 256, 0, stream>>>(d, count, scratch);
 }
 
-template <typename T>
+template <class Acc>
 __global__ void __launch_bounds__(256)
-    sample_kernel(const typename CxT<T>::type* __restrict__ a, int B,
+    sample_kernel(const typename Acc::in_t* __restrict__ a, int B,
                   uint64_t nblocks, const double* __restrict__ P,
                   uint64_t shots, uint64_t seed, uint64_t* __restrict__ out) {
   const uint64_t j = uint64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
@@ -377,7 +390,7 @@ __global__ void __launch_bounds__(256)
   for (int e = 0; e < 16; ++e) {
     p[e] = 0.0;
     if (lane < lanes && e < E) {
-      p[e] = prob_of(a[(b << B) + uint64_t(lane) * E + e]);
+      p[e] = Acc::p(a[(b << B) + uint64_t(lane) * E + e]);
       loc += p[e];
     }
   }
@@ -422,30 +435,45 @@ size_t sample_scratch_bytes(int n, uint64_t shots) {
          size_t(shots) * sizeof(uint64_t);
 }
 
-hipError_t launch_sample(int prec, const void* amp, int n, uint64_t shots,
-                         uint64_t seed, void* scratch, uint64_t* out_dev,
-                         hipStream_t stream) {
+template <class Acc>
+static void sample_dispatch(const void* src, int n, uint64_t shots,
+                            uint64_t seed, void* scratch, uint64_t* out_dev,
+                            hipStream_t stream) {
+  using In = typename Acc::in_t;
+  const In* a = static_cast<const In*>(src);
   const int B = sample_block_log(n);
   const uint64_t nb = uint64_t(1) << (n - B);
   double* P = static_cast<double*>(scratch);
   double* sc = P + nb;
-  const unsigned wb = unsigned((nb + 3) / 4);
-  if (prec == 1)
-    sample_blocksum_kernel<float><<<wb, 256, 0, stream>>>(
-        static_cast<const float2*>(amp), B, nb, P);
-  else
-    sample_blocksum_kernel<double><<<wb, 256, 0, stream>>>(
-        static_cast<const double2*>(amp), B, nb, P);
+  sample_blocksum_kernel<Acc><<<unsigned((nb + 3) / 4), 256, 0, stream>>>(
+      a, B, nb, P);
   scan_inclusive(P, nb, sc, stream);
-  const unsigned sb = unsigned((shots + 3) / 4);
-  if (shots) {
-    if (prec == 1)
-      sample_kernel<float><<<sb, 256, 0, stream>>>(
-          static_cast<const float2*>(amp), B, nb, P, shots, seed, out_dev);
-    else
-      sample_kernel<double><<<sb, 256, 0, stream>>>(
-          static_cast<const double2*>(amp), B, nb, P, shots, seed, out_dev);
-  }
+  if (shots)
+    sample_kernel<Acc><<<unsigned((shots + 3) / 4), 256, 0, stream>>>(
+        a, B, nb, P, shots, seed, out_dev);
+}
+
+hipError_t launch_sample(int prec, const void* amp, int n, uint64_t shots,
+                         uint64_t seed, void* scratch, uint64_t* out_dev,
+                         hipStream_t stream) {
+  if (prec == 1)
+    sample_dispatch<FromAmps<float>>(amp, n, shots, seed, scratch, out_dev,
+                                     stream);
+  else
+    sample_dispatch<FromAmps<double>>(amp, n, shots, seed, scratch, out_dev,
+                                      stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_probs(int fp64, const void* probs, int n,
+                               uint64_t shots, uint64_t seed, void* scratch,
+                               uint64_t* out_dev, hipStream_t stream) {
+  if (fp64)
+    sample_dispatch<FromProbs<double>>(probs, n, shots, seed, scratch, out_dev,
+                                       stream);
+  else
+    sample_dispatch<FromProbs<float>>(probs, n, shots, seed, scratch, out_dev,
+                                      stream);
   return hipGetLastError();
 }
 

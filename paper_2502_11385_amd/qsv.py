@@ -48,6 +48,9 @@ EXPORTED = [
     "qsv_set_profiling", "qsv_pass_times",
     "qsv_batch_create", "qsv_batch_out_offsets", "qsv_batch_launch",
     "qsv_batch_stats", "qsv_batch_free", "qsv_gate_matrices",
+    "qsv_server_create", "qsv_server_submit", "qsv_server_wait",
+    "qsv_server_release", "qsv_server_stats", "qsv_server_destroy",
+    "qsv_clock",
 ]
 
 
@@ -87,6 +90,27 @@ class qsv_batch_opts(C.Structure):
                 ("use_graph", C.c_int32), ("out_fp64", C.c_int32)]
 
 
+class qsv_server_opts(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("max_batch", C.c_int32),
+                ("small_width", C.c_int32), ("n_streams", C.c_int32),
+                ("serial", C.c_int32)]
+
+
+class qsv_request(C.Structure):
+    _fields_ = [("width", C.c_int32), ("prec", C.c_int32),
+                ("body", qsv_circuit), ("want_samples", C.c_int32),
+                ("shots", C.c_uint64), ("seed", C.c_uint64)]
+
+
+class qsv_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("width", C.c_int32),
+                ("prec", C.c_int32), ("is_samples", C.c_int32),
+                ("batched", C.c_int32), ("pad", C.c_int32),
+                ("n_out", C.c_uint64), ("data", C.c_void_p),
+                ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
 _p = C.c_void_p
 _i32 = C.c_int32
 _u64 = C.c_uint64
@@ -123,6 +147,12 @@ _SIGS = {
     "qsv_batch_launch": [_p, _p],
     "qsv_batch_stats": [_p, _pu64, _i32],
     "qsv_batch_free": [_p],
+    "qsv_server_create": [C.POINTER(qsv_server_opts), C.POINTER(_p)],
+    "qsv_server_submit": [_p, C.POINTER(qsv_request), _pu64],
+    "qsv_server_wait": [_p, _u64, C.POINTER(qsv_result)],
+    "qsv_server_release": [_p, _u64],
+    "qsv_server_stats": [_p, _pu64, _i32],
+    "qsv_server_destroy": [_p],
     "qsv_pass_times": [_p, C.POINTER(C.c_float), _pi32, _i32, _pi32],
 }
 for _name, _args in _SIGS.items():
@@ -133,6 +163,8 @@ _lib.qsv_last_error.restype = C.c_char_p
 _lib.qsv_last_error.argtypes = []
 _lib.qsv_version.restype = C.c_char_p
 _lib.qsv_version.argtypes = []
+_lib.qsv_clock.restype = C.c_double
+_lib.qsv_clock.argtypes = []
 
 
 def lib():
@@ -495,5 +527,78 @@ class Batch:
         try:
             if self._h:
                 _lib.qsv_batch_free(self._h)
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- serving
+
+def clock() -> float:
+    """The library's steady clock (seconds)."""
+    return _lib.qsv_clock()
+
+
+class Server:
+    """Request server with admission by HBM bytes and continuous batching."""
+
+    def __init__(self, budget_bytes: int = 0, max_batch: int = 0,
+                 small_width: int = 0, n_streams: int = 0,
+                 serial: bool = False):
+        o = qsv_server_opts(budget_bytes, max_batch, small_width, n_streams,
+                            int(serial))
+        self._h = C.c_void_p()
+        _check(_lib.qsv_server_create(C.byref(o), C.byref(self._h)))
+
+    def submit(self, width: int, circ: Circuit, prec: int = QSV_C64,
+               shots: int = 0, seed: int = 0) -> int:
+        """Enqueue a circuit on |0..0>; shots > 0 asks for samples."""
+        req = qsv_request(width, prec, circ.struct(), int(shots > 0),
+                          int(shots), int(seed))
+        t = C.c_uint64(0)
+        _check(_lib.qsv_server_submit(self._h, C.byref(req), C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, copy: bool = True):
+        """(data, info) for a finished request; data is a NumPy copy of the
+        probabilities (float32/float64) or samples (uint64)."""
+        r = qsv_result()
+        st = _lib.qsv_server_wait(self._h, ticket, C.byref(r))
+        info = {"status": r.status, "width": r.width, "prec": r.prec,
+                "samples": bool(r.is_samples), "batched": bool(r.batched),
+                "t_submit": r.t_submit, "t_admit": r.t_admit,
+                "t_start": r.t_start, "t_done": r.t_done}
+        _check(st)
+        if r.is_samples:
+            ct = C.c_uint64
+            dt = np.uint64
+        elif r.prec == QSV_C64:
+            ct, dt = C.c_float, np.float32
+        else:
+            ct, dt = C.c_double, np.float64
+        data = None
+        if copy and r.n_out:
+            buf = (ct * r.n_out).from_address(r.data)
+            data = np.frombuffer(buf, dtype=dt).copy()
+        return data, info
+
+    def release(self, ticket: int):
+        _check(_lib.qsv_server_release(self._h, ticket))
+
+    def stats(self) -> dict:
+        out = np.zeros(7, np.uint64)
+        _check(_lib.qsv_server_stats(self._h, _ptr(out, C.c_uint64), 7))
+        keys = ("submitted", "completed", "batch_launches", "single_launches",
+                "peak_reserved_bytes", "max_groups_in_flight", "rejected")
+        return {k: int(v) for k, v in zip(keys, out)}
+
+    def close(self):
+        if self._h:
+            _check(_lib.qsv_server_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._h:
+                _lib.qsv_server_destroy(self._h)
         except Exception:
             pass
