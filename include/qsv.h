@@ -180,6 +180,15 @@ qsv_status qsv_plan_describe(const qsv_circuit* circ, int32_t n_qubits,
                              int32_t* pass_kind, uint64_t* pass_qubits,
                              int32_t* n_passes);
 
+/* Testing aid (host only, no device work): plan the circuit with the
+ * tiled strategy for n_qubits <= 16, build the exact device program the
+ * tile kernel would run (passes, register segments, folded and merged
+ * ops) and execute it on the host in complex128 on `state` (2^n
+ * interleaved re/im doubles, updated in place).  Lets the planner's
+ * reordering and gate merging be checked on a machine without a GPU. */
+qsv_status qsv_debug_emulate_tiled(const qsv_circuit* circ, int32_t n_qubits,
+                                   const qsv_fuse_opts* opts, double* state);
+
 /* Standard gate matrix by name into out (2^k x 2^k complex, interleaved),
  * with *k_out its target count.  Names: "h","x","y","z","s","sdg","p"(1),
  * "u3"(3: theta, phi, lambda; the OpenQASM 2 U3, used as u3 in the

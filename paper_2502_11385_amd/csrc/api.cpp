@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -577,6 +578,109 @@ qsv_status qsv_plan_describe(const qsv_circuit* circ, int32_t n, int32_t prec,
     }
   }
   *n_passes = int32_t(plan.passes.size());
+  return QSV_OK;
+}
+
+qsv_status qsv_debug_emulate_tiled(const qsv_circuit* circ, int32_t n,
+                                   const qsv_fuse_opts* opts, double* state) {
+  if (n < 6 || n > 16) return fail(QSV_ERR_INVALID_ARG, "n must be 6..16");
+  if (!state) return fail(QSV_ERR_INVALID_ARG, "null state");
+  qsv_fuse_opts o = {};
+  if (opts) o = *opts;
+  o.strategy = QSV_PLAN_TILED;
+  std::vector<HostGate> G;
+  PlanOptions po;
+  Plan plan;
+  // the complex64 option set (it allows reg_log2 = 5); the host
+  // execution below is complex128 either way
+  qsv_status st = plan_for(circ, n, QSV_C64, &o, &G, &po, &plan);
+  if (st != QSV_OK) return st;
+  const uint64_t dim = uint64_t(1) << n;
+  auto C = [&](uint64_t i) { return std::complex<double>(state[2 * i], state[2 * i + 1]); };
+  auto put = [&](uint64_t i, std::complex<double> v) {
+    state[2 * i] = v.real();
+    state[2 * i + 1] = v.imag();
+  };
+  for (const Pass& p : plan.passes) {
+    if (p.kind != kPassTile) {  // plain gate: apply directly
+      const HostGate& g = G[p.gates[0]];
+      const int d = 1 << g.k;
+      std::vector<std::complex<double>> v(d);
+      for (uint64_t i = 0; i < dim; ++i) {
+        if ((i & g.tmask) || (i & g.cmask) != g.cmask) continue;
+        std::vector<uint64_t> idx(d);
+        for (int r = 0; r < d; ++r) {
+          uint64_t x = i;
+          for (int j = 0; j < g.k; ++j)
+            if (r >> j & 1) x |= uint64_t(1) << g.t[j];
+          idx[r] = x;
+          v[r] = C(x);
+        }
+        for (int r = 0; r < d; ++r) {
+          std::complex<double> acc = 0;
+          for (int c = 0; c < d; ++c)
+            acc += std::complex<double>(g.m[2 * (r * d + c)],
+                                        g.m[2 * (r * d + c) + 1]) * v[c];
+          put(idx[r], acc);
+        }
+      }
+      continue;
+    }
+    std::vector<TilePass> tp;
+    std::vector<TileSeg> ts;
+    std::vector<TileOp> to;
+    std::string err = emit_tile_pass(p, G, po.reg_log2, &tp, &ts, &to);
+    if (!err.empty()) return fail(QSV_ERR_DEVICE, err);
+    const int L = p.L;
+    const uint64_t tiles = uint64_t(1) << (n - L);
+    for (uint64_t tix = 0; tix < tiles; ++tix) {
+      uint64_t base = tix;
+      for (int b = 0; b < L; ++b) {
+        const int q = p.q[b];
+        base = ((base >> q) << (q + 1)) | (base & ((uint64_t(1) << q) - 1));
+      }
+      auto gidx = [&](uint32_t r) {
+        uint64_t x = base;
+        for (int b = 0; b < L; ++b)
+          if (r >> b & 1) x |= uint64_t(1) << p.q[b];
+        return x;
+      };
+      for (const TileSeg& sg : ts) {
+        for (int oi = sg.op_begin; oi < sg.op_end; ++oi) {
+          const TileOp& op = to[oi];
+          if ((base & op.gctrl) != op.gctrl) continue;
+          for (uint32_t r = 0; r < (1u << L); ++r) {
+            if ((r & op.lctrl) != op.lctrl) continue;
+            if (op.kind == kOpDense1) {
+              const int tb = sg.reg_bits[op.reg];
+              if (r >> tb & 1) continue;
+              const uint32_t r1 = r | (1u << tb);
+              bool second = false;
+              if (op.mux != kMuxNone)
+                second = op.mux >= 0 ? ((r >> op.mux) & 1)
+                                     : ((base >> (-1 - op.mux)) & 1);
+              const double* m = second ? op.m2 : op.m;
+              const std::complex<double> x0 = C(gidx(r)), x1 = C(gidx(r1));
+              const std::complex<double> m00(m[0], m[1]), m01(m[2], m[3]),
+                  m10(m[4], m[5]), m11(m[6], m[7]);
+              put(gidx(r), m00 * x0 + m01 * x1);
+              put(gidx(r1), m10 * x0 + m11 * x1);
+            } else if (op.kind == kOpPhase) {
+              put(gidx(r), C(gidx(r)) * std::complex<double>(op.m[0], op.m[1]));
+            } else {
+              auto bit = [&](int db) -> int {
+                return db >= 0 ? int(r >> db & 1) : int(base >> (-1 - db) & 1);
+              };
+              int e = bit(op.dbit0);
+              if (op.dk > 1) e |= bit(op.dbit1) << 1;
+              put(gidx(r), C(gidx(r)) *
+                               std::complex<double>(op.m[2 * e], op.m[2 * e + 1]));
+            }
+          }
+        }
+      }
+    }
+  }
   return QSV_OK;
 }
 

@@ -19,14 +19,12 @@
 
 namespace qsv {
 
-// At most 512 threads per tile (L - RB <= 9), which leaves up to 256 VGPRs
-// per lane for the register-resident tile.
+// One tile pass per work-group.  At most 512 threads per tile (L - RB <= 9).
 template <typename T, int RB>
-__global__ void __launch_bounds__(512)
-    tile_kernel(typename CxT<T>::type* __restrict__ amp,
-                const TilePass* __restrict__ pass,
-                const TileSeg* __restrict__ segs,
-                const TileOp* __restrict__ ops) {
+__device__ __forceinline__ void tile_body(typename CxT<T>::type* __restrict__ amp,
+                                          const TilePass* __restrict__ pass,
+                                          const TileSeg* __restrict__ segs,
+                                          const TileOp* __restrict__ ops) {
   using C = typename CxT<T>::type;
   constexpr int R = 1 << RB;
   extern __shared__ double lds_raw[];
@@ -49,6 +47,26 @@ __global__ void __launch_bounds__(512)
   for (int j = 0; j < R; ++j) amp[io_addr<RB>(gthr, greg, j)] = a[j];
 }
 
+// complex64 with 16 registers per thread: capped at 128 VGPRs so that four
+// waves share each SIMD (the tile is HBM- and VALU-bound; occupancy hides
+// both latencies).
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+    tile_kernel_c64_rb4(float2* __restrict__ amp,
+                        const TilePass* __restrict__ pass,
+                        const TileSeg* __restrict__ segs,
+                        const TileOp* __restrict__ ops) {
+  tile_body<float, 4>(amp, pass, segs, ops);
+}
+
+template <typename T, int RB>
+__global__ void __launch_bounds__(512)
+    tile_kernel(typename CxT<T>::type* __restrict__ amp,
+                const TilePass* __restrict__ pass,
+                const TileSeg* __restrict__ segs,
+                const TileOp* __restrict__ ops) {
+  tile_body<T, RB>(amp, pass, segs, ops);
+}
+
 template <typename T, int RB>
 static hipError_t tile_launch(void* amp, int n, int L, const TilePass* pass,
                               const TileSeg* segs, const TileOp* ops,
@@ -57,16 +75,22 @@ static hipError_t tile_launch(void* amp, int n, int L, const TilePass* pass,
   const size_t lds = size_t(sizeof(C)) << L;
   static bool attr_set = false;
   if (!attr_set) {
+    const void* fn = (sizeof(T) == 4 && RB == 4)
+                         ? reinterpret_cast<const void*>(&tile_kernel_c64_rb4)
+                         : reinterpret_cast<const void*>(&tile_kernel<T, RB>);
     hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&tile_kernel<T, RB>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   const unsigned threads = 1u << (L - RB);
   const uint64_t tiles = uint64_t(1) << (n - L);
-  tile_kernel<T, RB><<<unsigned(tiles), threads, lds, stream>>>(
-      static_cast<C*>(amp), pass, segs, ops);
+  if constexpr (sizeof(T) == 4 && RB == 4)
+    tile_kernel_c64_rb4<<<unsigned(tiles), threads, lds, stream>>>(
+        static_cast<C*>(amp), pass, segs, ops);
+  else
+    tile_kernel<T, RB><<<unsigned(tiles), threads, lds, stream>>>(
+        static_cast<C*>(amp), pass, segs, ops);
   return hipGetLastError();
 }
 
@@ -77,8 +101,10 @@ hipError_t launch_tile(int prec, int rb, void* amp, int n, int L,
   if (prec == 1)
     return rb == 4 ? tile_launch<float, 4>(amp, n, L, pass, segs, ops, stream)
                    : tile_launch<float, 5>(amp, n, L, pass, segs, ops, stream);
-  return rb == 4 ? tile_launch<double, 4>(amp, n, L, pass, segs, ops, stream)
-                 : tile_launch<double, 5>(amp, n, L, pass, segs, ops, stream);
+  // complex128 tiles always use 16 registers per thread (the planner
+  // rejects reg_log2 = 5 for them: 32 double2 registers would spill)
+  if (rb != 4) return hipErrorInvalidValue;
+  return tile_launch<double, 4>(amp, n, L, pass, segs, ops, stream);
 }
 
 }  // namespace qsv

@@ -230,6 +230,22 @@ static void plan_fused(const std::vector<HostGate>& G, int n, int b,
   }
 }
 
+// Value of diagonal gate d on a basis state given by `bits` (only the
+// qubits of d matter): its diagonal entry where all controls are 1, else 1.
+static void diag_value(const HostGate& d, uint64_t bits, double* re,
+                       double* im) {
+  if ((bits & d.cmask) != d.cmask) {
+    *re = 1;
+    *im = 0;
+    return;
+  }
+  int r = 0;
+  for (int j = 0; j < d.k; ++j) r |= int(bits >> d.t[j] & 1) << j;
+  const int dim = 1 << d.k;
+  *re = d.m[2 * (r * dim + r)];
+  *im = d.m[2 * (r * dim + r) + 1];
+}
+
 std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
                            int RB, std::vector<TilePass>* tpasses,
                            std::vector<TileSeg>* tsegs,
@@ -243,56 +259,215 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
     tp.q[j] = p.q[j];
     local_of[p.q[j]] = j;
   }
-  for (const auto& sg : p.segs) {
+  auto place_ctrl = [&](TileOp* op, uint64_t mask) {
+    for (int q = 0; q < 64; ++q)
+      if (mask >> q & 1) {
+        if (p.qubits >> q & 1)
+          op->lctrl |= 1u << local_of[q];
+        else
+          op->gctrl |= uint64_t(1) << q;
+      }
+  };
+  auto emit_diag = [&](const HostGate& g) {
+    TileOp op = {};
+    op.mux = kMuxNone;
+    place_ctrl(&op, g.cmask);
+    const int d = 1 << g.k;
+    if (g.masked_phase) {
+      op.kind = kOpPhase;
+      place_ctrl(&op, g.tmask);
+      op.m[0] = g.m[2 * ((d - 1) * d + (d - 1))];
+      op.m[1] = g.m[2 * ((d - 1) * d + (d - 1)) + 1];
+    } else {
+      op.kind = kOpDiag;
+      op.dk = g.k;
+      int* db[2] = {&op.dbit0, &op.dbit1};
+      for (int j = 0; j < g.k; ++j) {
+        const int q = g.t[j];
+        *db[j] = (p.qubits >> q & 1) ? local_of[q] : -1 - q;
+      }
+      for (int r = 0; r < d; ++r) {
+        op.m[2 * r] = g.m[2 * (r * d + r)];
+        op.m[2 * r + 1] = g.m[2 * (r * d + r) + 1];
+      }
+    }
+    for (int e = 0; e < 8; ++e) op.mf[e] = float(op.m[e]);
+    tops->push_back(op);
+  };
+
+  // Dense one-target gates are emitted as "mux" gates: matrix M(v) for each
+  // value v of at most one other qubit (a single control c becomes
+  // M(0) = I, M(1) = U).  Diagonal gates wait in `pend` until a dense gate
+  // acts on one of their qubits (they commute with everything else) and
+  // are folded into it when they involve at most that mux qubit:
+  // M(v) <- M(v) diag(e_0(v), e_1(v)).  A new gate on t then merges into
+  // the previous op on t when no op emitted since touches t and the mux
+  // qubit's value cannot have changed in between (no dense op on it since):
+  // M(v) <- M_new(v) M_prev(v).  The state after the pass is unchanged up
+  // to rounding.
+  const int n_q = 64;
+  std::vector<int> last_touch(n_q, -1), last_dense(n_q, -1);
+  const int op_base = int(tops->size());
+  auto touch_op = [&](uint64_t mask, int idx) {
+    for (int q = 0; q < n_q; ++q)
+      if (mask >> q & 1) last_touch[q] = std::max(last_touch[q], idx);
+  };
+  auto mux_code = [&](int q) -> int32_t {
+    return q < 0 ? kMuxNone
+                 : ((p.qubits >> q & 1) ? local_of[q] : -1 - q);
+  };
+  // mux qubit and dense target of each op emitted in this pass (-1: none)
+  std::vector<int> op_mux_q, op_target_q;
+  auto emit_diag_tracked = [&](const HostGate& g) {
+    emit_diag(g);
+    op_mux_q.push_back(-1);
+    op_target_q.push_back(-1);
+    touch_op(g.touch(), int(tops->size()) - 1);
+  };
+  std::vector<int> pend;
+  for (size_t si = 0; si < p.segs.size(); ++si) {
+    const auto& sg = p.segs[si];
     TileSeg ts = {};
     for (int i = 0; i < RB; ++i) ts.reg_bits[i] = sg.reg_bits[i];
     ts.op_begin = int32_t(tops->size());
     for (int gi : sg.gates) {
       const HostGate& g = G[gi];
-      TileOp op = {};
-      for (int j = 0; j < g.c; ++j) {
-        const int q = g.ctl[j];
-        if (p.qubits >> q & 1)
-          op.lctrl |= 1u << local_of[q];
-        else
-          op.gctrl |= uint64_t(1) << q;
+      if (g.diagonal) {
+        pend.push_back(gi);
+        continue;
       }
-      const int d = 1 << g.k;
-      if (!g.diagonal) {
-        op.kind = kOpDense1;
-        const int lb = local_of[g.t[0]];
-        op.reg = -1;
-        for (int i = 0; i < RB; ++i)
-          if (sg.reg_bits[i] == lb) op.reg = i;
-        if (op.reg < 0)
-          return "internal planner error: target not in a register bit";
-        for (int e = 0; e < 8; ++e) op.m[e] = g.m[e];
-      } else if (g.masked_phase) {
-        op.kind = kOpPhase;
-        for (int j = 0; j < g.k; ++j) {
-          const int q = g.t[j];
-          if (p.qubits >> q & 1)
-            op.lctrl |= 1u << local_of[q];
-          else
-            op.gctrl |= uint64_t(1) << q;
-        }
-        op.m[0] = g.m[2 * ((d - 1) * d + (d - 1))];
-        op.m[1] = g.m[2 * ((d - 1) * d + (d - 1)) + 1];
+      const int t = g.t[0];
+      std::vector<int> hit, keep;
+      for (int d : pend)
+        (G[d].touch() >> t & 1 ? hit : keep).push_back(d);
+      pend.swap(keep);
+      // the gate as mux matrices
+      int mux_q = -1;
+      bool plain = g.c > 1;  // more than one control: a controlled op
+      double M[2][8];
+      if (g.c == 1) {
+        mux_q = g.ctl[0];
+        const double id[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+        std::memcpy(M[0], id, sizeof id);
+        std::memcpy(M[1], g.m.data(), sizeof M[1]);
       } else {
-        op.kind = kOpDiag;
-        op.dk = g.k;
-        int* db[2] = {&op.dbit0, &op.dbit1};
-        for (int j = 0; j < g.k; ++j) {
-          const int q = g.t[j];
-          *db[j] = (p.qubits >> q & 1) ? local_of[q] : -1 - q;
-        }
-        for (int r = 0; r < d; ++r) {
-          op.m[2 * r] = g.m[2 * (r * d + r)];
-          op.m[2 * r + 1] = g.m[2 * (r * d + r) + 1];
+        std::memcpy(M[0], g.m.data(), sizeof M[0]);
+        std::memcpy(M[1], g.m.data(), sizeof M[1]);
+      }
+      bool fold = !plain;
+      for (int d : hit) {
+        const uint64_t others = G[d].touch() & ~(uint64_t(1) << t);
+        if (__builtin_popcountll(others) > 1) fold = false;
+        if (others) {
+          const int q = __builtin_ctzll(others);
+          if (mux_q < 0 && fold) mux_q = q;
+          else if (mux_q != q) fold = false;
         }
       }
-      for (int e = 0; e < 8; ++e) op.mf[e] = float(op.m[e]);
-      tops->push_back(op);
+      if (!fold) {
+        for (int d : hit) emit_diag_tracked(G[d]);
+        if (!plain && g.c == 0) mux_q = -1;
+        if (!plain && g.c == 1) mux_q = g.ctl[0];
+      } else {
+        for (int v = 0; v < 2; ++v)
+          for (int sc = 0; sc < 2; ++sc) {  // column sc scaled by e_sc(v)
+            double er = 1, ei = 0;
+            const uint64_t bits = (uint64_t(sc) << t) |
+                                  (mux_q >= 0 ? uint64_t(v) << mux_q : 0);
+            for (int d : hit) {
+              double vr, vi;
+              diag_value(G[d], bits, &vr, &vi);
+              const double nr = er * vr - ei * vi, ni = er * vi + ei * vr;
+              er = nr;
+              ei = ni;
+            }
+            for (int r = 0; r < 2; ++r) {
+              double* x = &M[v][2 * (2 * r + sc)];
+              const double xr = x[0], xi = x[1];
+              x[0] = xr * er - xi * ei;
+              x[1] = xr * ei + xi * er;
+            }
+          }
+      }
+      const int lb = local_of[t];
+      int reg = -1;
+      for (int i = 0; i < RB; ++i)
+        if (sg.reg_bits[i] == lb) reg = i;
+      if (reg < 0) return "internal planner error: target not in a register bit";
+      // merge into the previous op on t?
+      const int prev = last_touch[t];
+      bool merged = false;
+      if (!plain && prev >= op_base) {
+        TileOp& po = (*tops)[prev];
+        const int pq = op_mux_q[prev - op_base];
+        if (po.kind == kOpDense1 && op_target_q[prev - op_base] == t &&
+            po.lctrl == 0 && po.gctrl == 0 &&
+            (pq < 0 || mux_q < 0 || pq == mux_q)) {
+          const int mq = pq >= 0 ? pq : mux_q;
+          // the mux qubit must keep its value from prev to here
+          const bool ok = mux_q < 0 || last_dense[mux_q] < prev;
+          if (ok) {
+            double out[2][8];
+            for (int v = 0; v < 2; ++v) {
+              const double* A = M[v];
+              const double* B = (pq >= 0 && v) ? po.m2 : po.m;
+              double* C2 = out[v];
+              for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 2; ++c) {
+                  double cr = 0, ci = 0;
+                  for (int k = 0; k < 2; ++k) {
+                    const double ar = A[2 * (2 * r + k)], ai = A[2 * (2 * r + k) + 1];
+                    const double br = B[2 * (2 * k + c)], bi = B[2 * (2 * k + c) + 1];
+                    cr += ar * br - ai * bi;
+                    ci += ar * bi + ai * br;
+                  }
+                  C2[2 * (2 * r + c)] = cr;
+                  C2[2 * (2 * r + c) + 1] = ci;
+                }
+            }
+            std::memcpy(po.m, out[0], sizeof out[0]);
+            std::memcpy(po.m2, out[1], sizeof out[1]);
+            po.mux = mux_code(mq);
+            op_mux_q[prev - op_base] = mq;
+            for (int e = 0; e < 8; ++e) {
+              po.mf[e] = float(po.m[e]);
+              po.mf2[e] = float(po.m2[e]);
+            }
+            if (mq >= 0) touch_op(uint64_t(1) << mq, prev);
+            merged = true;
+          }
+        }
+      }
+      if (!merged) {
+        TileOp op = {};
+        op.kind = kOpDense1;
+        op.reg = reg;
+        op.mux = kMuxNone;
+        if (plain) {
+          place_ctrl(&op, g.cmask);
+          for (int e = 0; e < 8; ++e) op.m[e] = g.m[e];
+        } else {
+          std::memcpy(op.m, M[0], sizeof op.m);
+          std::memcpy(op.m2, M[1], sizeof op.m2);
+          op.mux = mux_code(mux_q);
+        }
+        for (int e = 0; e < 8; ++e) {
+          op.mf[e] = float(op.m[e]);
+          op.mf2[e] = float(op.m2[e]);
+        }
+        tops->push_back(op);
+        op_mux_q.push_back(plain ? -1 : mux_q);
+        op_target_q.push_back(t);
+        const int idx = int(tops->size()) - 1;
+        touch_op(g.touch() | (mux_q >= 0 ? uint64_t(1) << mux_q : 0), idx);
+        last_dense[t] = idx;
+      } else {
+        last_dense[t] = std::max(last_dense[t], prev);
+      }
+    }
+    if (si + 1 == p.segs.size()) {
+      for (int d : pend) emit_diag_tracked(G[d]);
+      pend.clear();
     }
     ts.op_end = int32_t(tops->size());
     tsegs->push_back(ts);

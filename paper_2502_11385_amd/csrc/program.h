@@ -20,7 +20,7 @@ enum : int32_t {
 
 // One gate inside a tile segment.
 //  kOpDense1: reg = index (0..RB-1) of the register bit holding the target;
-//             m = 2x2 complex matrix, row-major interleaved.
+//             m = 2x2 complex matrix, row-major interleaved (see mux below).
 //  kOpDiag:   dk targets (1 or 2); dbit[j] >= 0 is the tile-local bit of
 //             target j, dbit[j] < 0 means qubit (-1 - dbit[j]) outside the
 //             tile (its value is fixed per tile); m holds the 2^dk diagonal
@@ -41,7 +41,16 @@ struct alignas(16) TileOp {
   uint64_t gctrl;
   double m[8];
   float mf[8];  // m rounded to FP32 (complex64 states)
+  // kOpDense1 only: the matrix may depend on one more qubit ("mux"):
+  // kMuxNone, a tile-local bit (>= 0) or an outer qubit q as -1 - q.  The
+  // op applies m where that bit is 0 and m2 where it is 1.
+  int32_t mux;
+  int32_t pad2;
+  double m2[8];
+  float mf2[8];
 };
+
+constexpr int32_t kMuxNone = -1000;
 
 // A run of ops executed with one register layout: the tile-local bits in
 // reg_bits[0..RB-1] (ascending) index each thread's registers; the other

@@ -45,6 +45,59 @@ __device__ __forceinline__ void dense1_regs(C* a, T m0r, T m0i, T m1r, T m1i,
   }
 }
 
+// The same update with the matrix chosen per pair by tile-local bit mbit:
+// m0 where the bit is 0, m1 where it is 1 (mbit differs from the target).
+template <int I, int R, bool CTRL, typename C, typename T>
+__device__ __forceinline__ void dense1_mux_regs(C* a, const T* m0,
+                                                const T* m1, uint32_t rt,
+                                                const uint32_t* lr,
+                                                uint32_t lctrl, int mbit) {
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    if (j & (1 << I)) continue;
+    const int j1 = j | (1 << I);
+    const bool sel = (((rt | lr[j]) >> mbit) & 1u) != 0;
+    T m[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) m[e] = sel ? m1[e] : m0[e];
+    const C x0 = a[j], x1 = a[j1];
+    C y0, y1;
+    y0.x = m[0] * x0.x - m[1] * x0.y + m[2] * x1.x - m[3] * x1.y;
+    y0.y = m[0] * x0.y + m[1] * x0.x + m[2] * x1.y + m[3] * x1.x;
+    y1.x = m[4] * x0.x - m[5] * x0.y + m[6] * x1.x - m[7] * x1.y;
+    y1.y = m[4] * x0.y + m[5] * x0.x + m[6] * x1.y + m[7] * x1.x;
+    if constexpr (CTRL) {
+      const bool on = ((rt | lr[j]) & lctrl) == lctrl;
+      a[j] = csel(on, y0, x0);
+      a[j1] = csel(on, y1, x1);
+    } else {
+      a[j] = y0;
+      a[j1] = y1;
+    }
+  }
+}
+
+template <int R, bool CTRL, typename C, typename T>
+__device__ __forceinline__ void dense1_mux_dispatch(int reg, C* a, const T* m0,
+                                                    const T* m1, uint32_t rt,
+                                                    const uint32_t* lr,
+                                                    uint32_t lctrl, int mbit) {
+#define QSV_D1M(I)                                                        \
+  case I:                                                                 \
+    if constexpr ((1 << I) < R)                                           \
+      dense1_mux_regs<I, R, CTRL>(a, m0, m1, rt, lr, lctrl, mbit);        \
+    break;
+  switch (reg) {
+    QSV_D1M(0)
+    QSV_D1M(1)
+    QSV_D1M(2)
+    QSV_D1M(3)
+    QSV_D1M(4)
+    QSV_D1M(5)
+  }
+#undef QSV_D1M
+}
+
 template <int R, bool CTRL, typename C, typename T>
 __device__ __forceinline__ void dense1_dispatch(int reg, C* a, const T* m,
                                                 uint32_t rt, const uint32_t* lr,
@@ -161,18 +214,32 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
       const int kind = op->kind;
       const uint32_t lctrl = op->lctrl;
       if (kind == kOpDense1) {
-        T m[8];
+        const int mux = op->mux;
+        // an outer mux qubit is fixed per tile: pick the matrix once
+        const bool second =
+            mux != kMuxNone && mux < 0 && ((base >> ((-1 - mux) & 63)) & 1);
+        T m[8], m2[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          if constexpr (sizeof(T) == 4)
-            m[e] = op->mf[e];
-          else
-            m[e] = op->m[e];
+          if constexpr (sizeof(T) == 4) {
+            m[e] = second ? op->mf2[e] : op->mf[e];
+            m2[e] = op->mf2[e];
+          } else {
+            m[e] = second ? op->m2[e] : op->m[e];
+            m2[e] = op->m2[e];
+          }
         }
-        if (lctrl)
+        if (mux >= 0) {
+          if (lctrl)
+            dense1_mux_dispatch<R, true>(op->reg, a, m, m2, rt, lr, lctrl, mux);
+          else
+            dense1_mux_dispatch<R, false>(op->reg, a, m, m2, rt, lr, lctrl,
+                                          mux);
+        } else if (lctrl) {
           dense1_dispatch<R, true>(op->reg, a, m, rt, lr, lctrl);
-        else
+        } else {
           dense1_dispatch<R, false>(op->reg, a, m, rt, lr, lctrl);
+        }
       } else if (kind == kOpPhase) {
         C ph;
         ph.x = T(op->m[0]);

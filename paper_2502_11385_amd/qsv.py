@@ -50,7 +50,7 @@ EXPORTED = [
     "qsv_batch_stats", "qsv_batch_free", "qsv_gate_matrices",
     "qsv_server_create", "qsv_server_submit", "qsv_server_wait",
     "qsv_server_release", "qsv_server_stats", "qsv_server_destroy",
-    "qsv_clock",
+    "qsv_clock", "qsv_debug_emulate_tiled",
 ]
 
 
@@ -131,6 +131,8 @@ _SIGS = {
                           _pu64, _pi32],
     "qsv_gate_matrix": [C.c_char_p, _pd, _i32, _pd, _pi32],
     "qsv_gate_matrices": [C.c_char_p, _pd, _i32, C.c_size_t, _pd],
+    "qsv_debug_emulate_tiled": [C.POINTER(qsv_circuit), _i32,
+                                C.POINTER(qsv_fuse_opts), _pd],
     "qsv_probabilities": [_p, _p, _i32],
     "qsv_norm": [_p, _pd],
     "qsv_renormalize": [_p, _pd],
@@ -314,6 +316,17 @@ def plan_describe(circ: Circuit, n: int, prec: int = QSV_C64,
     p = npass.value
     n_g = len(circ)
     return gate_pass[:n_g], gate_order[:n_g], pass_kind[:p], pass_qubits[:p]
+
+
+def debug_emulate_tiled(circ: Circuit, n: int, state: np.ndarray,
+                        opts: Optional[qsv_fuse_opts] = None) -> np.ndarray:
+    """Host emulation of the tiled device program (testing aid)."""
+    v = np.ascontiguousarray(np.asarray(state, dtype=np.complex128)).copy()
+    st = circ.struct()
+    _check(_lib.qsv_debug_emulate_tiled(
+        C.byref(st), n, C.byref(opts) if opts is not None else None,
+        v.ctypes.data_as(C.POINTER(C.c_double))))
+    return v
 
 
 # ---------------------------------------------------------------- states

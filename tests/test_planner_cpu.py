@@ -128,3 +128,76 @@ def test_pass_counts_30q_layered():
     _, _, fk, _ = qsv.plan_describe(circ, 30, qsv.QSV_C64,
                                     qsv.fuse_opts(strategy=qsv.PLAN_FUSED))
     assert len(fk) < 1780
+
+
+# --------------------------------------------------------------------------
+# the emitted tile program (register segments, folded diagonals, merged
+# gates), executed on the host, against the oracle
+
+
+def _cut_variant_gates(seed, w):
+    from circuits import batch_variants
+    v = batch_variants(1, seed=seed, wmin=w, wmax=w, dmin=6, dmax=6)[0]
+    return (oracle.cut_prologue(v.cut_inputs) + list(v.gates) +
+            oracle.cut_epilogue(v.cut_outputs))
+
+
+EMU_CASES = CASES + [
+    ("variant10", 10, lambda: _cut_variant_gates(3, 10)),
+    ("variant12", 12, lambda: _cut_variant_gates(4, 12)),
+    ("mixed12", 12, lambda: _mixed(12, 300, 17)),
+]
+
+
+@pytest.mark.parametrize("opts", [
+    dict(), dict(tile_log2=8, low_qubits=2), dict(tile_log2=9, reg_log2=5),
+    dict(tile_log2=10, low_qubits=3)])
+@pytest.mark.parametrize("name,n,make", EMU_CASES)
+def test_emulated_tile_program_matches_oracle(name, n, make, opts):
+    gates = make()
+    v = random_state(n, 5)
+    want = oracle.simulate(n, gates, init=v)
+    got = qsv.debug_emulate_tiled(qsv.Circuit.from_gates(gates), n, v,
+                                  qsv.fuse_opts(**opts))
+    assert np.max(np.abs(got - want)) < 1e-12
+
+
+def _random_mixed_with_diagonals(n, count, seed):
+    """Gates of every kind the tile program handles: dense 1-qubit gates
+    with 0-2 controls, masked phases and general 1-2 qubit diagonals."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        kind = int(rng.integers(0, 7))
+        qs = [int(v) for v in rng.choice(n, 3, replace=False)]
+        if kind <= 1:
+            u = qsv.gate_matrix("u3", rng.uniform(0, 6, 3))
+            out.append((u, qs[:1], qs[1:1 + kind]))
+        elif kind == 2:
+            out.append((qsv.gate_matrix("x"), qs[:1], qs[1:3]))   # Toffoli
+        elif kind == 3:
+            out.append((np.diag([1, -1]).astype(complex), qs[:1], qs[1:2]))
+        elif kind == 4:
+            out.append((np.diag(np.exp(1j * rng.uniform(0, 6, 2))), qs[:1],
+                        []))
+        elif kind == 5:
+            out.append((np.diag(np.exp(1j * rng.uniform(0, 6, 4))), qs[:2],
+                        []))
+        else:
+            out.append((np.diag([1, np.exp(1j * 0.7)]), qs[:1], qs[1:3]))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("n,L", [(10, 8), (11, 9), (9, 9)])
+def test_emulated_random_programs(seed, n, L):
+    gl = _random_mixed_with_diagonals(n, 160, seed)
+    circ = qsv.Circuit()
+    want = random_state(n, seed)
+    v = want.copy()
+    for u, t, c in gl:
+        circ.add(t, u, c)
+        want = oracle.apply_gate(want, n, np.asarray(u, complex), t, c)
+    got = qsv.debug_emulate_tiled(circ, n, v,
+                                  qsv.fuse_opts(tile_log2=L, low_qubits=2))
+    assert np.max(np.abs(got - want)) < 1e-12
