@@ -482,7 +482,8 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
     }
     if (p.kind == kPassTile) {
       QSV_HIP(s, launch_tile(s->prec, po.reg_log2, s->amp, n, p.L,
-                             d_tp + ti, d_ts, d_to, s->stream));
+                             tpasses[ti].boff32 != 0, d_tp + ti, d_ts, d_to,
+                             s->stream));
       ++ti;
     } else if (p.kind == kPassPlain) {
       const HostGate& g = G[p.gates[0]];
@@ -648,6 +649,16 @@ qsv_status qsv_debug_emulate_tiled(const qsv_circuit* circ, int32_t n,
       for (const TileSeg& sg : ts) {
         for (int oi = sg.op_begin; oi < sg.op_end; ++oi) {
           const TileOp& op = to[oi];
+          // the kernels trust mux_reg to name the mux bit's register
+          const bool mux_in_reg = op.kind == kOpDense1 && op.mux >= 0 &&
+                                  [&] {
+                                    for (int i = 0; i < po.reg_log2; ++i)
+                                      if (sg.reg_bits[i] == op.mux) return true;
+                                    return false;
+                                  }();
+          if ((op.mux_reg >= 0) != mux_in_reg ||
+              (op.mux_reg >= 0 && sg.reg_bits[op.mux_reg] != op.mux))
+            return fail(QSV_ERR_DEVICE, "tile op has an inconsistent mux_reg");
           if ((base & op.gctrl) != op.gctrl) continue;
           for (uint32_t r = 0; r < (1u << L); ++r) {
             if ((r & op.lctrl) != op.lctrl) continue;

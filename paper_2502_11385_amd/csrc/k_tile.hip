@@ -20,7 +20,10 @@
 namespace qsv {
 
 // One tile pass per work-group.  At most 512 threads per tile (L - RB <= 9).
-template <typename T, int RB>
+// BOFF32: the I/O layout's thread byte offsets fit 32 bits (decided on the
+// host per pass), so loads and stores use a uniform per-register pointer
+// plus a 32-bit per-thread offset and need no 64-bit vector address math.
+template <typename T, int RB, bool BOFF32>
 __device__ __forceinline__ void tile_body(typename CxT<T>::type* __restrict__ amp,
                                           const TilePass* __restrict__ pass,
                                           const TileSeg* __restrict__ segs,
@@ -37,37 +40,57 @@ __device__ __forceinline__ void tile_body(typename CxT<T>::type* __restrict__ am
   // HBM transfers use the I/O layout: registers select the top RB tile bits
   // and consecutive threads take consecutive low tile bits, so a wave's
   // accesses are contiguous runs of the lowest (always tile) qubits.
-  uint64_t gthr, greg[RB];
-  io_offsets<RB>(pass, base, tid, &gthr, greg);
   C a[R];
+  if constexpr (BOFF32) {
+    C* tile = amp + base;
+    const uint32_t boff = io_thread_boff<C, RB>(pass, tid);
 #pragma unroll
-  for (int j = 0; j < R; ++j) a[j] = amp[io_addr<RB>(gthr, greg, j)];
-  tile_apply<T, RB>(a, lds, pass, segs, ops, base, tid, true);
+    for (int j = 0; j < R; ++j)
+      a[j] = load_at(tile, io_reg_rsrc<C, RB>(tile, pass, j), boff);
+    tile_apply<T, RB>(a, lds, pass, segs, ops, base, tid, true);
 #pragma unroll
-  for (int j = 0; j < R; ++j) amp[io_addr<RB>(gthr, greg, j)] = a[j];
+    for (int j = 0; j < R; ++j)
+      store_at(io_reg_rsrc<C, RB>(tile, pass, j), boff, a[j]);
+  } else {
+    uint64_t gthr, greg[RB];
+    io_offsets<RB>(pass, base, tid, &gthr, greg);
+#pragma unroll
+    for (int j = 0; j < R; ++j) a[j] = amp[io_addr<RB>(gthr, greg, j)];
+    tile_apply<T, RB>(a, lds, pass, segs, ops, base, tid, true);
+#pragma unroll
+    for (int j = 0; j < R; ++j) amp[io_addr<RB>(gthr, greg, j)] = a[j];
+  }
 }
 
 // complex64 with 16 registers per thread: capped at 128 VGPRs so that four
-// waves share each SIMD (the tile is HBM- and VALU-bound; occupancy hides
-// both latencies).
+// waves share each SIMD (occupancy hides HBM and VALU latencies).
+template <bool BOFF32>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
     tile_kernel_c64_rb4(float2* __restrict__ amp,
                         const TilePass* __restrict__ pass,
                         const TileSeg* __restrict__ segs,
                         const TileOp* __restrict__ ops) {
-  tile_body<float, 4>(amp, pass, segs, ops);
+  tile_body<float, 4, BOFF32>(amp, pass, segs, ops);
 }
 
-template <typename T, int RB>
+template <typename T, int RB, bool BOFF32>
 __global__ void __launch_bounds__(512)
     tile_kernel(typename CxT<T>::type* __restrict__ amp,
                 const TilePass* __restrict__ pass,
                 const TileSeg* __restrict__ segs,
                 const TileOp* __restrict__ ops) {
-  tile_body<T, RB>(amp, pass, segs, ops);
+  tile_body<T, RB, BOFF32>(amp, pass, segs, ops);
 }
 
-template <typename T, int RB>
+template <typename T, int RB, bool BOFF32>
+static const void* tile_fn() {
+  if constexpr (sizeof(T) == 4 && RB == 4)
+    return reinterpret_cast<const void*>(&tile_kernel_c64_rb4<BOFF32>);
+  else
+    return reinterpret_cast<const void*>(&tile_kernel<T, RB, BOFF32>);
+}
+
+template <typename T, int RB, bool BOFF32>
 static hipError_t tile_launch(void* amp, int n, int L, const TilePass* pass,
                               const TileSeg* segs, const TileOp* ops,
                               hipStream_t stream) {
@@ -75,36 +98,39 @@ static hipError_t tile_launch(void* amp, int n, int L, const TilePass* pass,
   const size_t lds = size_t(sizeof(C)) << L;
   static bool attr_set = false;
   if (!attr_set) {
-    const void* fn = (sizeof(T) == 4 && RB == 4)
-                         ? reinterpret_cast<const void*>(&tile_kernel_c64_rb4)
-                         : reinterpret_cast<const void*>(&tile_kernel<T, RB>);
-    hipError_t e = hipFuncSetAttribute(
-        fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipError_t e = hipFuncSetAttribute(tile_fn<T, RB, BOFF32>(),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   const unsigned threads = 1u << (L - RB);
   const uint64_t tiles = uint64_t(1) << (n - L);
   if constexpr (sizeof(T) == 4 && RB == 4)
-    tile_kernel_c64_rb4<<<unsigned(tiles), threads, lds, stream>>>(
+    tile_kernel_c64_rb4<BOFF32><<<unsigned(tiles), threads, lds, stream>>>(
         static_cast<C*>(amp), pass, segs, ops);
   else
-    tile_kernel<T, RB><<<unsigned(tiles), threads, lds, stream>>>(
+    tile_kernel<T, RB, BOFF32><<<unsigned(tiles), threads, lds, stream>>>(
         static_cast<C*>(amp), pass, segs, ops);
   return hipGetLastError();
 }
 
 hipError_t launch_tile(int prec, int rb, void* amp, int n, int L,
-                       const TilePass* pass, const TileSeg* segs,
+                       bool boff32, const TilePass* pass, const TileSeg* segs,
                        const TileOp* ops, hipStream_t stream) {
   if (L - rb < 0 || L - rb > 9 || n - L > 31) return hipErrorInvalidValue;
-  if (prec == 1)
-    return rb == 4 ? tile_launch<float, 4>(amp, n, L, pass, segs, ops, stream)
-                   : tile_launch<float, 5>(amp, n, L, pass, segs, ops, stream);
+#define QSV_T(T, RBV)                                                        \
+  return boff32 ? tile_launch<T, RBV, true>(amp, n, L, pass, segs, ops, stream) \
+                : tile_launch<T, RBV, false>(amp, n, L, pass, segs, ops, stream)
+  if (prec == 1) {
+    if (rb == 4) QSV_T(float, 4);
+    QSV_T(float, 5);
+  }
   // complex128 tiles always use 16 registers per thread (the planner
   // rejects reg_log2 = 5 for them: 32 double2 registers would spill)
   if (rb != 4) return hipErrorInvalidValue;
-  return tile_launch<double, 4>(amp, n, L, pass, segs, ops, stream);
+  QSV_T(double, 4);
+#undef QSV_T
 }
 
 }  // namespace qsv

@@ -254,6 +254,10 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
   tp.L = p.L;
   tp.nseg = int32_t(p.segs.size());
   tp.seg_begin = int32_t(tsegs->size());
+  // Thread bits of the I/O layout are tile bits 0..L-RB-1.  Their largest
+  // byte offset, below 16 * 2^(q[L-RB-1]+1) even for complex128, must stay
+  // below 2^31 for the buffer-resource (32-bit offset) addressing.
+  tp.boff32 = (p.L - RB <= 0) || (p.q[p.L - RB - 1] + 1 + 4 <= 31);
   int local_of[64];
   for (int j = 0; j < p.L; ++j) {
     tp.q[j] = p.q[j];
@@ -471,6 +475,20 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
     }
     ts.op_end = int32_t(tops->size());
     tsegs->push_back(ts);
+  }
+  // Locate each op's tile-local mux bit in its own segment's register bits
+  // (merges above may have changed an op's mux after its segment closed).
+  for (size_t si = 0; si < p.segs.size(); ++si) {
+    const TileSeg& ts = (*tsegs)[tp.seg_begin + si];
+    for (int oi = ts.op_begin; oi < ts.op_end; ++oi) {
+      TileOp& op = (*tops)[oi];
+      op.mux_reg = -1;
+      if (op.kind != kOpDense1 || op.mux == kMuxNone || op.mux < 0) continue;
+      for (int i = 0; i < RB; ++i)
+        if (ts.reg_bits[i] == op.mux) op.mux_reg = i;
+      if (op.mux_reg == op.reg)
+        return "internal planner error: mux bit equals the target bit";
+    }
   }
   tpasses->push_back(tp);
   return "";

@@ -45,7 +45,10 @@ struct alignas(16) TileOp {
   // kMuxNone, a tile-local bit (>= 0) or an outer qubit q as -1 - q.  The
   // op applies m where that bit is 0 and m2 where it is 1.
   int32_t mux;
-  int32_t pad2;
+  // kOpDense1 with a tile-local mux bit: the index of the register bit that
+  // holds it in the op's segment, or -1 when a thread bit holds it (then the
+  // matrix is fixed per thread).  -1 for every other op.
+  int32_t mux_reg;
   double m2[8];
   float mf2[8];
 };
@@ -67,7 +70,7 @@ struct alignas(16) TilePass {
   int32_t L;
   int32_t nseg;
   int32_t seg_begin;
-  int32_t pad;
+  int32_t boff32;  // 1: thread byte offsets of the I/O layout fit 32 bits
   int32_t q[16];
 };
 

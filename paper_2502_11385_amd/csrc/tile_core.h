@@ -84,9 +84,12 @@ __device__ __forceinline__ void dense1_mux_dispatch(int reg, C* a, const T* m0,
                                                     uint32_t lctrl, int mbit) {
 #define QSV_D1M(I)                                                        \
   case I:                                                                 \
-    if constexpr ((1 << I) < R)                                           \
+    if constexpr ((1 << I) < R) {                                         \
       dense1_mux_regs<I, R, CTRL>(a, m0, m1, rt, lr, lctrl, mbit);        \
-    break;
+      break;                                                              \
+    } else {                                                              \
+      __builtin_unreachable();                                            \
+    }
   switch (reg) {
     QSV_D1M(0)
     QSV_D1M(1)
@@ -94,6 +97,8 @@ __device__ __forceinline__ void dense1_mux_dispatch(int reg, C* a, const T* m0,
     QSV_D1M(3)
     QSV_D1M(4)
     QSV_D1M(5)
+    default:
+      __builtin_unreachable();  // the planner emits reg < RB only
   }
 #undef QSV_D1M
 }
@@ -104,10 +109,13 @@ __device__ __forceinline__ void dense1_dispatch(int reg, C* a, const T* m,
                                                 uint32_t lctrl) {
 #define QSV_D1(I)                                                          \
   case I:                                                                  \
-    if constexpr ((1 << I) < R)                                            \
+    if constexpr ((1 << I) < R) {                                          \
       dense1_regs<I, R, CTRL>(a, m[0], m[1], m[2], m[3], m[4], m[5], m[6], \
                               m[7], rt, lr, lctrl);                        \
-    break;
+      break;                                                               \
+    } else {                                                               \
+      __builtin_unreachable();                                             \
+    }
   switch (reg) {
     QSV_D1(0)
     QSV_D1(1)
@@ -115,8 +123,58 @@ __device__ __forceinline__ void dense1_dispatch(int reg, C* a, const T* m,
     QSV_D1(3)
     QSV_D1(4)
     QSV_D1(5)
+    default:
+      __builtin_unreachable();  // the planner emits reg < RB only
   }
 #undef QSV_D1
+}
+
+// The mux update when the mux bit is register bit K of the segment: which
+// matrix a pair takes is known at compile time, both matrices are uniform.
+template <int I, int K, int R, typename C, typename T>
+__device__ __forceinline__ void dense1_muxreg_regs(C* a, const T* m0,
+                                                   const T* m1) {
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    if (j & (1 << I)) continue;
+    const int j1 = j | (1 << I);
+    const T* m = (j >> K & 1) ? m1 : m0;
+    const C x0 = a[j], x1 = a[j1];
+    C y0, y1;
+    y0.x = m[0] * x0.x - m[1] * x0.y + m[2] * x1.x - m[3] * x1.y;
+    y0.y = m[0] * x0.y + m[1] * x0.x + m[2] * x1.y + m[3] * x1.x;
+    y1.x = m[4] * x0.x - m[5] * x0.y + m[6] * x1.x - m[7] * x1.y;
+    y1.y = m[4] * x0.y + m[5] * x0.x + m[6] * x1.y + m[7] * x1.x;
+    a[j] = y0;
+    a[j1] = y1;
+  }
+}
+
+template <int R, typename C, typename T>
+__device__ __forceinline__ void dense1_muxreg_dispatch(int reg, int k, C* a,
+                                                       const T* m0,
+                                                       const T* m1) {
+#define QSV_D1K(I, K)                                                     \
+  case I * 8 + K:                                                         \
+    if constexpr ((1 << I) < R && (1 << K) < R && I != K) {               \
+      dense1_muxreg_regs<I, K, R>(a, m0, m1);                             \
+      break;                                                              \
+    } else {                                                              \
+      __builtin_unreachable();                                            \
+    }
+#define QSV_D1K_ROW(I) \
+  QSV_D1K(I, 0) QSV_D1K(I, 1) QSV_D1K(I, 2) QSV_D1K(I, 3) QSV_D1K(I, 4)
+  switch (reg * 8 + k) {
+    QSV_D1K_ROW(0)
+    QSV_D1K_ROW(1)
+    QSV_D1K_ROW(2)
+    QSV_D1K_ROW(3)
+    QSV_D1K_ROW(4)
+    default:
+      __builtin_unreachable();  // reg, k < RB <= 5 and reg != k
+  }
+#undef QSV_D1K_ROW
+#undef QSV_D1K
 }
 
 // Register layout: reg_bits[i] (ascending) is the tile-local bit selecting
@@ -160,18 +218,21 @@ __device__ __forceinline__ void relayout(C* a, C* lds, const Layout<RB>& from,
                                          const Layout<RB>& to, uint32_t tid,
                                          bool active) {
   constexpr int R = 1 << RB;
+  // The swizzle is linear over XOR and the thread and register parts of a
+  // tile index have disjoint bits, so swz(rt | o_j) = swz(rt) ^ swz(o_j):
+  // one per-thread term and one uniform term per register.
   if (active) {
-    const uint32_t rf = thread_local_base(from, tid);
+    const uint32_t rf = lds_swz<T>(thread_local_base(from, tid));
 #pragma unroll
     for (int j = 0; j < R; ++j)
-      lds[lds_swz<T>(rf | reg_offset(from, j))] = a[j];
+      lds[rf ^ lds_swz<T>(reg_offset(from, j))] = a[j];
   }
   __syncthreads();
   if (active) {
-    const uint32_t rt = thread_local_base(to, tid);
+    const uint32_t rt = lds_swz<T>(thread_local_base(to, tid));
 #pragma unroll
     for (int j = 0; j < R; ++j)
-      a[j] = lds[lds_swz<T>(rt | reg_offset(to, j))];
+      a[j] = lds[rt ^ lds_swz<T>(reg_offset(to, j))];
   }
   __syncthreads();
 }
@@ -229,12 +290,18 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
             m2[e] = op->m2[e];
           }
         }
-        if (mux >= 0) {
-          if (lctrl)
-            dense1_mux_dispatch<R, true>(op->reg, a, m, m2, rt, lr, lctrl, mux);
-          else
-            dense1_mux_dispatch<R, false>(op->reg, a, m, m2, rt, lr, lctrl,
-                                          mux);
+        const int mreg = op->mux_reg;
+        if (mux >= 0 && lctrl == 0 && mreg >= 0) {
+          // mux bit in a register: the pairs' matrices are fixed
+          dense1_muxreg_dispatch<R>(op->reg, mreg, a, m, m2);
+        } else if (mux >= 0 && lctrl == 0) {
+          // mux bit in the thread index: one matrix per thread
+          const bool sel = ((rt >> mux) & 1u) != 0;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) m[e] = sel ? m2[e] : m[e];
+          dense1_dispatch<R, false>(op->reg, a, m, rt, lr, lctrl);
+        } else if (mux >= 0) {
+          dense1_mux_dispatch<R, true>(op->reg, a, m, m2, rt, lr, lctrl, mux);
         } else if (lctrl) {
           dense1_dispatch<R, true>(op->reg, a, m, rt, lr, lctrl);
         } else {
@@ -295,6 +362,67 @@ __device__ __forceinline__ void io_offsets(const TilePass* pass, uint64_t base,
   *gthr = g;
 #pragma unroll
   for (int i = 0; i < RB; ++i) greg[i] = uint64_t(1) << pass->q[W + i];
+}
+
+// I/O addressing with a uniform per-register pointer and a per-thread
+// 32-bit byte offset (valid when the thread part of the tile index times
+// the amplitude size fits in 32 bits): register j of thread tid is at
+// byte  (tile + sum over set bits i of j of 2^q[W+i]) + thread_off.
+template <typename C, int RB>
+__device__ __forceinline__ uint32_t io_thread_boff(const TilePass* pass,
+                                                   uint32_t tid) {
+  const int W = pass->L - RB;
+  uint32_t o = 0;
+  for (int b = 0; b < W; ++b)
+    if (tid >> b & 1) o |= 1u << pass->q[b];
+  return o * uint32_t(sizeof(C));
+}
+
+// Buffer resource of register j's slice of the tile: a uniform base address
+// (the tile base plus register j's fixed offset) with raw byte addressing.
+// Each access is then "scalar resource + 32-bit per-thread offset", which
+// costs no per-access 64-bit vector address arithmetic.
+template <typename C, int RB>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t io_reg_rsrc(
+    C* tile, const TilePass* pass, int j) {
+  const int W = pass->L - RB;
+  uint64_t o = 0;
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+    if (j >> i & 1) o |= uint64_t(1) << pass->q[W + i];
+  // the address is the same in every lane: keep it in scalar registers
+  const uint64_t a = reinterpret_cast<uint64_t>(tile + o);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(a));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
+  void* p = reinterpret_cast<void*>((uint64_t(hi) << 32) | lo);
+  // stride 0 (raw), the full 32-bit byte range, gfx9 word-3 layout with a
+  // 32-bit data format; offsets used here stay below 2^31
+  return __builtin_amdgcn_make_buffer_rsrc(p, short(0), int(0xffffffffu),
+                                           0x00020000);
+}
+
+__device__ __forceinline__ float2 load_at(const float2*,
+                                          __amdgpu_buffer_rsrc_t r,
+                                          uint32_t boff) {
+  return __builtin_bit_cast(float2,
+                            __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+}
+__device__ __forceinline__ double2 load_at(const double2*,
+                                           __amdgpu_buffer_rsrc_t r,
+                                           uint32_t boff) {
+  return __builtin_bit_cast(double2,
+                            __builtin_amdgcn_raw_buffer_load_b128(r, boff, 0, 0));
+}
+__device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r,
+                                         uint32_t boff, float2 v) {
+  using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, boff, 0, 0);
+}
+__device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r,
+                                         uint32_t boff, double2 v) {
+  using V = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, v), r, boff, 0,
+                                         0);
 }
 
 template <int RB>
