@@ -123,13 +123,13 @@ typedef enum {
 } qsv_strategy;
 
 /* Options of qsv_apply_fused; all-zero (or NULL) selects defaults.
- *   tile_log2  : tile size L (amplitudes per tile = 2^L), 10..13
- *                (default 12 for c64, 11 for c128)
+ *   tile_log2  : tile size L (amplitudes per tile = 2^L), 8..13, with
+ *                L - reg_log2 <= 9 (default 12 for c64, 11 for c128)
  *   k_max      : widest fused block, 1..5 (default 5)
  *   low_qubits : qubits 0..low_qubits-1 belong to every tile so that HBM
  *                accesses are contiguous runs (default 5 c64, 4 c128)
- *   reg_log2   : amplitudes per thread inside a tile, as log2 (4 or 5;
- *                default 4)
+ *   reg_log2   : amplitudes per thread inside a tile, as log2: 3, 4 or 5
+ *                (5 for c64 only; default 4)
  * This is the single-GPU form of the chunking and cache blocking of
  * Section III.B: a tile of 2^L amplitudes plays the role of a 2^nc chunk
  * (blocking_qubits), and the planner reorders commuting gates so that runs

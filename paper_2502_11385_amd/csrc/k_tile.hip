@@ -19,10 +19,39 @@
 
 namespace qsv {
 
-// One tile pass per work-group.  At most 512 threads per tile (L - RB <= 9).
-// BOFF32: the I/O layout's thread byte offsets fit 32 bits (decided on the
-// host per pass), so loads and stores use a uniform per-register pointer
-// plus a 32-bit per-thread offset and need no 64-bit vector address math.
+// Byte offset of register j of the I/O layout within a tile (uniform).
+template <typename C, int RB>
+__device__ __forceinline__ void io_reg_offsets(const TilePass* pass,
+                                               uint64_t* roff) {
+  const int W = pass->L - RB;
+  roff[0] = 0;
+#pragma unroll
+  for (int j = 1; j < (1 << RB); ++j) {
+    const int i = __builtin_ctz(j);
+    roff[j] = roff[j & (j - 1)] + (uint64_t(sizeof(C)) << pass->q[W + i]);
+  }
+}
+
+// Tile index -> global index of the tile's first amplitude: the index's
+// bits spread over the non-tile qubits.
+__device__ __forceinline__ uint64_t tile_base(const TilePass* pass,
+                                              uint32_t tile) {
+  uint64_t base = tile;
+  const int L = pass->L;
+  for (int b = 0; b < L; ++b) base = insert_zero64(base, pass->q[b]);
+  return base;
+}
+
+template <typename C>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* p) {
+  // stride 0 (raw), the full 32-bit byte range, gfx9 word-3 layout with a
+  // 32-bit data format; offsets used here stay below 2^31
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), short(0),
+                                           int(0xffffffffu), 0x00020000);
+}
+
+// One tile per work-group.  At most 512 threads per tile (L - RB <= 9).
+// BOFF32 as for the persistent kernel; otherwise 64-bit addressing.
 template <typename T, int RB, bool BOFF32>
 __device__ __forceinline__ void tile_body(typename CxT<T>::type* __restrict__ amp,
                                           const TilePass* __restrict__ pass,
@@ -32,25 +61,23 @@ __device__ __forceinline__ void tile_body(typename CxT<T>::type* __restrict__ am
   constexpr int R = 1 << RB;
   extern __shared__ double lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
-  const int L = pass->L;
   const uint32_t tid = threadIdx.x;
-  // Tile base: the block index spread over the non-tile qubits.
-  uint64_t base = blockIdx.x;
-  for (int b = 0; b < L; ++b) base = insert_zero64(base, pass->q[b]);
+  const uint64_t base = tile_base(pass, blockIdx.x);
   // HBM transfers use the I/O layout: registers select the top RB tile bits
   // and consecutive threads take consecutive low tile bits, so a wave's
   // accesses are contiguous runs of the lowest (always tile) qubits.
   C a[R];
   if constexpr (BOFF32) {
-    C* tile = amp + base;
     const uint32_t boff = io_thread_boff<C, RB>(pass, tid);
+    uint64_t roff[R];
+    io_reg_offsets<C, RB>(pass, roff);
+    const char* tile = reinterpret_cast<const char*>(amp + base);
 #pragma unroll
     for (int j = 0; j < R; ++j)
-      a[j] = load_at(tile, io_reg_rsrc<C, RB>(tile, pass, j), boff);
+      a[j] = load_at(amp, raw_rsrc<C>(tile + roff[j]), boff);
     tile_apply<T, RB>(a, lds, pass, segs, ops, base, tid, true);
 #pragma unroll
-    for (int j = 0; j < R; ++j)
-      store_at(io_reg_rsrc<C, RB>(tile, pass, j), boff, a[j]);
+    for (int j = 0; j < R; ++j) store_at(raw_rsrc<C>(tile + roff[j]), boff, a[j]);
   } else {
     uint64_t gthr, greg[RB];
     io_offsets<RB>(pass, base, tid, &gthr, greg);
@@ -63,7 +90,7 @@ __device__ __forceinline__ void tile_body(typename CxT<T>::type* __restrict__ am
 }
 
 // complex64 with 16 registers per thread: capped at 128 VGPRs so that four
-// waves share each SIMD (occupancy hides HBM and VALU latencies).
+// waves share each SIMD.
 template <bool BOFF32>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
     tile_kernel_c64_rb4(float2* __restrict__ amp,
@@ -82,15 +109,16 @@ __global__ void __launch_bounds__(512)
   tile_body<T, RB, BOFF32>(amp, pass, segs, ops);
 }
 
-template <typename T, int RB, bool BOFF32>
+// Kernel variants: 0 = 64-bit addressing, 1 = 32-bit offsets.
+template <typename T, int RB, int V>
 static const void* tile_fn() {
   if constexpr (sizeof(T) == 4 && RB == 4)
-    return reinterpret_cast<const void*>(&tile_kernel_c64_rb4<BOFF32>);
+    return reinterpret_cast<const void*>(&tile_kernel_c64_rb4<V == 1>);
   else
-    return reinterpret_cast<const void*>(&tile_kernel<T, RB, BOFF32>);
+    return reinterpret_cast<const void*>(&tile_kernel<T, RB, V == 1>);
 }
 
-template <typename T, int RB, bool BOFF32>
+template <typename T, int RB, int V>
 static hipError_t tile_launch(void* amp, int n, int L, const TilePass* pass,
                               const TileSeg* segs, const TileOp* ops,
                               hipStream_t stream) {
@@ -98,7 +126,7 @@ static hipError_t tile_launch(void* amp, int n, int L, const TilePass* pass,
   const size_t lds = size_t(sizeof(C)) << L;
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(tile_fn<T, RB, BOFF32>(),
+    hipError_t e = hipFuncSetAttribute(tile_fn<T, RB, V>(),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        160 * 1024);
     if (e != hipSuccess) return e;
@@ -106,30 +134,44 @@ static hipError_t tile_launch(void* amp, int n, int L, const TilePass* pass,
   }
   const unsigned threads = 1u << (L - RB);
   const uint64_t tiles = uint64_t(1) << (n - L);
-  if constexpr (sizeof(T) == 4 && RB == 4)
-    tile_kernel_c64_rb4<BOFF32><<<unsigned(tiles), threads, lds, stream>>>(
+  if constexpr (sizeof(T) == 4 && RB == 4) {
+    tile_kernel_c64_rb4<V == 1><<<unsigned(tiles), threads, lds, stream>>>(
         static_cast<C*>(amp), pass, segs, ops);
-  else
-    tile_kernel<T, RB, BOFF32><<<unsigned(tiles), threads, lds, stream>>>(
+  } else {
+    tile_kernel<T, RB, V == 1><<<unsigned(tiles), threads, lds, stream>>>(
         static_cast<C*>(amp), pass, segs, ops);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_tile(int prec, int rb, void* amp, int n, int L,
                        bool boff32, const TilePass* pass, const TileSeg* segs,
                        const TileOp* ops, hipStream_t stream) {
-  if (L - rb < 0 || L - rb > 9 || n - L > 31) return hipErrorInvalidValue;
-#define QSV_T(T, RBV)                                                        \
-  return boff32 ? tile_launch<T, RBV, true>(amp, n, L, pass, segs, ops, stream) \
-                : tile_launch<T, RBV, false>(amp, n, L, pass, segs, ops, stream)
+  if (L - rb < 0 || L - rb > 9 || L > kMaxTileBits || n - L > 31)
+    return hipErrorInvalidValue;
+#define QSV_T(T, RBV, V) return tile_launch<T, RBV, V>(amp, n, L, pass, segs, ops, stream)
   if (prec == 1) {
-    if (rb == 4) QSV_T(float, 4);
-    QSV_T(float, 5);
+    if (rb == 3) {
+      if (boff32) QSV_T(float, 3, 1);
+      QSV_T(float, 3, 0);
+    }
+    if (rb == 4) {
+      if (boff32) QSV_T(float, 4, 1);
+      QSV_T(float, 4, 0);
+    }
+    if (rb != 5) return hipErrorInvalidValue;
+    if (boff32) QSV_T(float, 5, 1);
+    QSV_T(float, 5, 0);
   }
-  // complex128 tiles always use 16 registers per thread (the planner
-  // rejects reg_log2 = 5 for them: 32 double2 registers would spill)
+  // complex128 tiles use 8 or 16 registers per thread (the planner rejects
+  // reg_log2 = 5 for them: 32 double2 registers would spill)
+  if (rb == 3) {
+    if (boff32) QSV_T(double, 3, 1);
+    QSV_T(double, 3, 0);
+  }
   if (rb != 4) return hipErrorInvalidValue;
-  QSV_T(double, 4);
+  if (boff32) QSV_T(double, 4, 1);
+  QSV_T(double, 4, 0);
 #undef QSV_T
 }
 

@@ -32,8 +32,10 @@ std::string resolve_options(int n, int bytes_per_amp, const int* v,
   if (r.k_max < 1 || r.k_max > kMaxK) return "k_max must be 1..5";
   if (r.low_qubits < 0 || r.low_qubits > r.tile_log2 - 1)
     return "low_qubits must be 0..tile_log2-1";
-  if (r.reg_log2 != 4 && r.reg_log2 != 5) return "reg_log2 must be 4 or 5";
+  if (r.reg_log2 < 3 || r.reg_log2 > 5) return "reg_log2 must be 3, 4 or 5";
   if (r.reg_log2 > r.tile_log2 - 2) return "reg_log2 too large for tile";
+  if (r.tile_log2 - r.reg_log2 > 9)
+    return "tile_log2 - reg_log2 must be <= 9 (512 threads per tile)";
   if (bytes_per_amp == 16 && r.reg_log2 > 4)
     return "reg_log2 must be 4 for complex128 (register budget)";
   (void)n;

@@ -35,7 +35,8 @@ __device__ __forceinline__ void dense1_regs(C* a, T m0r, T m0i, T m1r, T m1i,
     y1.x = m2r * x0.x - m2i * x0.y + m3r * x1.x - m3i * x1.y;
     y1.y = m2r * x0.y + m2i * x0.x + m3r * x1.y + m3i * x1.x;
     if constexpr (CTRL) {
-      const bool on = ((rt | lr[j]) & lctrl) == lctrl;
+      // rt and lr[j] have disjoint bits: test the thread part once
+      const bool on = ((rt & lctrl) | (lr[j] & lctrl)) == lctrl;
       a[j] = csel(on, y0, x0);
       a[j1] = csel(on, y1, x1);
     } else {
@@ -56,7 +57,7 @@ __device__ __forceinline__ void dense1_mux_regs(C* a, const T* m0,
   for (int j = 0; j < R; ++j) {
     if (j & (1 << I)) continue;
     const int j1 = j | (1 << I);
-    const bool sel = (((rt | lr[j]) >> mbit) & 1u) != 0;
+    const bool sel = (((rt >> mbit) | (lr[j] >> mbit)) & 1u) != 0;
     T m[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) m[e] = sel ? m1[e] : m0[e];
@@ -67,7 +68,7 @@ __device__ __forceinline__ void dense1_mux_regs(C* a, const T* m0,
     y1.x = m[4] * x0.x - m[5] * x0.y + m[6] * x1.x - m[7] * x1.y;
     y1.y = m[4] * x0.y + m[5] * x0.x + m[6] * x1.y + m[7] * x1.x;
     if constexpr (CTRL) {
-      const bool on = ((rt | lr[j]) & lctrl) == lctrl;
+      const bool on = ((rt & lctrl) | (lr[j] & lctrl)) == lctrl;
       a[j] = csel(on, y0, x0);
       a[j1] = csel(on, y1, x1);
     } else {
@@ -211,6 +212,24 @@ __device__ __forceinline__ uint32_t reg_offset(const Layout<RB>& lay, int j) {
   return o;
 }
 
+// LDS byte offsets of a layout's registers, swz(reg_offset(j)) * sizeof(C),
+// as uniform values.  The swizzle is linear over XOR, so the offsets are
+// XOR combinations of one value per register bit.
+template <typename T, int RB>
+__device__ __forceinline__ void lds_reg_offsets(const Layout<RB>& lay,
+                                                uint32_t* so) {
+  using C = typename CxT<T>::type;
+  uint32_t basis[RB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+    basis[i] = __builtin_amdgcn_readfirstlane(
+        lds_swz<T>(1u << lay.rb[i]) * uint32_t(sizeof(C)));
+  so[0] = 0;
+#pragma unroll
+  for (int j = 1; j < (1 << RB); ++j)
+    so[j] = so[j & (j - 1)] ^ basis[__builtin_ctz(j)];
+}
+
 // Move the tile from layout `from` to layout `to` through LDS.
 // Threads with active == false (beyond the tile) only join the barriers.
 template <typename T, int RB, typename C>
@@ -218,21 +237,25 @@ __device__ __forceinline__ void relayout(C* a, C* lds, const Layout<RB>& from,
                                          const Layout<RB>& to, uint32_t tid,
                                          bool active) {
   constexpr int R = 1 << RB;
-  // The swizzle is linear over XOR and the thread and register parts of a
-  // tile index have disjoint bits, so swz(rt | o_j) = swz(rt) ^ swz(o_j):
-  // one per-thread term and one uniform term per register.
+  // The thread and register parts of a tile index have disjoint bits and
+  // the swizzle is linear over XOR: swz(rt | o_j) = swz(rt) ^ swz(o_j), one
+  // per-thread term and one uniform term per register.
+  char* lb = reinterpret_cast<char*>(lds);
+  uint32_t so[R];
   if (active) {
-    const uint32_t rf = lds_swz<T>(thread_local_base(from, tid));
+    lds_reg_offsets<T, RB>(from, so);
+    const uint32_t rf =
+        lds_swz<T>(thread_local_base(from, tid)) * uint32_t(sizeof(C));
 #pragma unroll
-    for (int j = 0; j < R; ++j)
-      lds[rf ^ lds_swz<T>(reg_offset(from, j))] = a[j];
+    for (int j = 0; j < R; ++j) *reinterpret_cast<C*>(lb + (rf ^ so[j])) = a[j];
   }
   __syncthreads();
   if (active) {
-    const uint32_t rt = lds_swz<T>(thread_local_base(to, tid));
+    lds_reg_offsets<T, RB>(to, so);
+    const uint32_t rt =
+        lds_swz<T>(thread_local_base(to, tid)) * uint32_t(sizeof(C));
 #pragma unroll
-    for (int j = 0; j < R; ++j)
-      a[j] = lds[rt ^ lds_swz<T>(reg_offset(to, j))];
+    for (int j = 0; j < R; ++j) a[j] = *reinterpret_cast<const C*>(lb + (rt ^ so[j]));
   }
   __syncthreads();
 }
@@ -309,11 +332,18 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
         }
       } else if (kind == kOpPhase) {
         C ph;
-        ph.x = T(op->m[0]);
-        ph.y = T(op->m[1]);
+        if constexpr (sizeof(T) == 4) {
+          ph.x = op->mf[0];
+          ph.y = op->mf[1];
+        } else {
+          ph.x = op->m[0];
+          ph.y = op->m[1];
+        }
+        // the index's thread and register parts have disjoint bits
+        const uint32_t tm = rt & lctrl;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-          const bool on = ((rt | lr[j]) & lctrl) == lctrl;
+          const bool on = (tm | (lr[j] & lctrl)) == lctrl;
           const C y = cmul(a[j], ph);
           a[j] = csel(on, y, a[j]);
         }
@@ -327,19 +357,28 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
         C t[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          t[e].x = T(op->m[2 * e]);
-          t[e].y = T(op->m[2 * e + 1]);
+          if constexpr (sizeof(T) == 4) {
+            t[e].x = op->mf[2 * e];
+            t[e].y = op->mf[2 * e + 1];
+          } else {
+            t[e].x = op->m[2 * e];
+            t[e].y = op->m[2 * e + 1];
+          }
         }
+        // thread parts of the two index bits, once per op
+        const uint32_t t0 = d0 >= 0 ? (rt >> (d0 & 31)) & 1u : g0;
+        const uint32_t t1 =
+            dk > 1 ? (d1 >= 0 ? (rt >> (d1 & 31)) & 1u : g1) : 0u;
+        const uint32_t tm = rt & lctrl;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-          const uint32_t r = rt | lr[j];
-          const uint32_t b0 = d0 >= 0 ? (r >> (d0 & 31)) & 1u : g0;
+          const uint32_t b0 = d0 >= 0 ? t0 | ((lr[j] >> (d0 & 31)) & 1u) : g0;
           const uint32_t b1 =
-              dk > 1 ? (d1 >= 0 ? (r >> (d1 & 31)) & 1u : g1) : 0u;
+              dk > 1 ? (d1 >= 0 ? t1 | ((lr[j] >> (d1 & 31)) & 1u) : g1) : 0u;
           const C f01 = csel(b0 != 0, t[1], t[0]);
           const C f23 = csel(b0 != 0, t[3], t[2]);
           const C f = csel(b1 != 0, f23, f01);
-          const bool on = (r & lctrl) == lctrl;
+          const bool on = (tm | (lr[j] & lctrl)) == lctrl;
           const C y = cmul(a[j], f);
           a[j] = csel(on, y, a[j]);
         }
@@ -378,29 +417,8 @@ __device__ __forceinline__ uint32_t io_thread_boff(const TilePass* pass,
   return o * uint32_t(sizeof(C));
 }
 
-// Buffer resource of register j's slice of the tile: a uniform base address
-// (the tile base plus register j's fixed offset) with raw byte addressing.
-// Each access is then "scalar resource + 32-bit per-thread offset", which
-// costs no per-access 64-bit vector address arithmetic.
-template <typename C, int RB>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t io_reg_rsrc(
-    C* tile, const TilePass* pass, int j) {
-  const int W = pass->L - RB;
-  uint64_t o = 0;
-#pragma unroll
-  for (int i = 0; i < RB; ++i)
-    if (j >> i & 1) o |= uint64_t(1) << pass->q[W + i];
-  // the address is the same in every lane: keep it in scalar registers
-  const uint64_t a = reinterpret_cast<uint64_t>(tile + o);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(a));
-  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
-  void* p = reinterpret_cast<void*>((uint64_t(hi) << 32) | lo);
-  // stride 0 (raw), the full 32-bit byte range, gfx9 word-3 layout with a
-  // 32-bit data format; offsets used here stay below 2^31
-  return __builtin_amdgcn_make_buffer_rsrc(p, short(0), int(0xffffffffu),
-                                           0x00020000);
-}
-
+// Raw buffer loads and stores at a 32-bit byte offset from a uniform buffer
+// resource (no per-access 64-bit vector address arithmetic).
 __device__ __forceinline__ float2 load_at(const float2*,
                                           __amdgpu_buffer_rsrc_t r,
                                           uint32_t boff) {

@@ -109,7 +109,8 @@ def test_plan_option_validation():
     with pytest.raises(qsv.QsvError) as e:
         qsv.plan_describe(c, 8, opts=qsv.fuse_opts(strategy=9))
     assert e.value.status == qsv.QSV_ERR_UNSUPPORTED
-    for kw in (dict(tile_log2=20), dict(k_max=7), dict(reg_log2=3)):
+    for kw in (dict(tile_log2=20), dict(k_max=7), dict(reg_log2=2),
+               dict(reg_log2=6), dict(tile_log2=13, reg_log2=3)):
         with pytest.raises(qsv.QsvError) as e:
             qsv.plan_describe(c, 8, opts=qsv.fuse_opts(**kw))
         assert e.value.status == qsv.QSV_ERR_INVALID_ARG

@@ -135,6 +135,9 @@ STRATS = {
     "tiled_L10_rb5": qsv.fuse_opts(strategy=qsv.PLAN_TILED, tile_log2=10,
                                    reg_log2=5, low_qubits=3),
     "tiled_L13": qsv.fuse_opts(strategy=qsv.PLAN_TILED, tile_log2=13),
+    "tiled_rb3": qsv.fuse_opts(strategy=qsv.PLAN_TILED, reg_log2=3),
+    "tiled_L9_rb3": qsv.fuse_opts(strategy=qsv.PLAN_TILED, tile_log2=9,
+                                  reg_log2=3, low_qubits=3),
     "tiled_L8": qsv.fuse_opts(strategy=qsv.PLAN_TILED, tile_log2=8,
                               low_qubits=2),
     "fused5": qsv.fuse_opts(strategy=qsv.PLAN_FUSED, k_max=5),

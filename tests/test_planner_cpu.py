@@ -151,7 +151,7 @@ EMU_CASES = CASES + [
 
 @pytest.mark.parametrize("opts", [
     dict(), dict(tile_log2=8, low_qubits=2), dict(tile_log2=9, reg_log2=5),
-    dict(tile_log2=10, low_qubits=3)])
+    dict(tile_log2=10, low_qubits=3), dict(tile_log2=10, reg_log2=3)])
 @pytest.mark.parametrize("name,n,make", EMU_CASES)
 def test_emulated_tile_program_matches_oracle(name, n, make, opts):
     gates = make()
