@@ -482,7 +482,7 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
     }
     if (p.kind == kPassTile) {
       QSV_HIP(s, launch_tile(s->prec, po.reg_log2, s->amp, n, p.L,
-                             tpasses[ti].boff32 != 0, d_tp + ti, d_ts, d_to,
+                             tpasses[ti].flags, d_tp + ti, d_ts, d_to,
                              s->stream));
       ++ti;
     } else if (p.kind == kPassPlain) {

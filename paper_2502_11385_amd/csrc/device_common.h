@@ -80,7 +80,7 @@ hipError_t launch_diag(int prec, void* amp, int n, const HostGate& g,
 // One tile pass: pass/segs/ops point into the device program buffer;
 // L is the pass's tile size and rb its register bits.
 hipError_t launch_tile(int prec, int rb, void* amp, int n, int L,
-                       bool boff32, const TilePass* pass, const TileSeg* segs,
+                       int32_t flags, const TilePass* pass, const TileSeg* segs,
                        const TileOp* ops, hipStream_t stream);
 // Build all fused unitaries (FP64, then rounded to FP32).
 hipError_t launch_fused_build(const FusedBlock* blocks, int n_blocks,

@@ -62,7 +62,12 @@ __device__ __forceinline__ void tile_body(typename CxT<T>::type* __restrict__ am
   extern __shared__ double lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
   const uint32_t tid = threadIdx.x;
-  const uint64_t base = tile_base(pass, blockIdx.x);
+  uint32_t tix = blockIdx.x;
+  if (pass->flags & kPassSpread) {
+    const uint32_t tb = 31u - __builtin_clz(gridDim.x);  // log2(#tiles)
+    tix = tb ? (__builtin_bitreverse32(tix) >> (32u - tb)) : 0u;
+  }
+  const uint64_t base = tile_base(pass, tix);
   // HBM transfers use the I/O layout: registers select the top RB tile bits
   // and consecutive threads take consecutive low tile bits, so a wave's
   // accesses are contiguous runs of the lowest (always tile) qubits.
@@ -145,8 +150,9 @@ static hipError_t tile_launch(void* amp, int n, int L, const TilePass* pass,
 }
 
 hipError_t launch_tile(int prec, int rb, void* amp, int n, int L,
-                       bool boff32, const TilePass* pass, const TileSeg* segs,
+                       int32_t flags, const TilePass* pass, const TileSeg* segs,
                        const TileOp* ops, hipStream_t stream) {
+  const bool boff32 = (flags & kPassBoff32) != 0;
   if (L - rb < 0 || L - rb > 9 || L > kMaxTileBits || n - L > 31)
     return hipErrorInvalidValue;
 #define QSV_T(T, RBV, V) return tile_launch<T, RBV, V>(amp, n, L, pass, segs, ops, stream)

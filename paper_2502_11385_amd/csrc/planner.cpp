@@ -259,7 +259,13 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
   // Thread bits of the I/O layout are tile bits 0..L-RB-1.  Their largest
   // byte offset, below 16 * 2^(q[L-RB-1]+1) even for complex128, must stay
   // below 2^31 for the buffer-resource (32-bit offset) addressing.
-  tp.boff32 = (p.L - RB <= 0) || (p.q[p.L - RB - 1] + 1 + 4 <= 31);
+  tp.flags = 0;
+  if ((p.L - RB <= 0) || (p.q[p.L - RB - 1] + 1 + 4 <= 31))
+    tp.flags |= kPassBoff32;
+  // the tile is 2^(L - m) contiguous runs, m = its lowest contiguous qubits
+  int m = 0;
+  while (m < p.L && p.q[m] == m) ++m;
+  if (p.L - m >= 3) tp.flags |= kPassSpread;
   int local_of[64];
   for (int j = 0; j < p.L; ++j) {
     tp.q[j] = p.q[j];

@@ -64,13 +64,24 @@ struct alignas(16) TileSeg {
   int32_t op_end;
 };
 
+// TilePass flags.
+//  kPassBoff32: the I/O layout's thread byte offsets fit 32 bits, so the
+//               kernel may address HBM as buffer resource + 32-bit offset.
+//  kPassSpread: work-group g takes tile bitreverse(g) instead of tile g, so
+//               that work-groups running at the same time touch far-apart
+//               parts of the state.  Used for tiles made of many short runs
+//               spaced by a large power of two, whose concurrent accesses
+//               otherwise crowd a few DRAM channels.
+constexpr int32_t kPassBoff32 = 1;
+constexpr int32_t kPassSpread = 2;
+
 // One tile pass: 2^L amplitudes per tile, tile-local bit b is global qubit
 // q[b] (ascending).  Tiles are the cosets of the other n - L qubits.
 struct alignas(16) TilePass {
   int32_t L;
   int32_t nseg;
   int32_t seg_begin;
-  int32_t boff32;  // 1: thread byte offsets of the I/O layout fit 32 bits
+  int32_t flags;  // kPassBoff32 | kPassSpread
   int32_t q[16];
 };
 
