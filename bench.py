@@ -29,12 +29,18 @@ PEAK_HBM_GBPS = 8000.0
 N_QUBITS, DEPTH, SEED = 30, 40, 30
 SHOTS, SAMPLE_SEED = 1_000_000, 1000003
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_kernel_30q_c64_traffic.json")
-TILE_SRC = os.path.join(ROOT, "paper_2502_11385_amd", "csrc", "k_tile.hip")
+# the sources the tile kernel is compiled from (kernel, core, records)
+TILE_SRC = [os.path.join(ROOT, "paper_2502_11385_amd", "csrc", f)
+            for f in ("k_tile.hip", "tile_core.h", "device_common.h",
+                      "program.h", "planner.cpp")]
 
 
-def _src_hash(path: str) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def _src_hash(paths) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 # --------------------------------------------------------------- CPU leg

@@ -178,11 +178,25 @@ __global__ void __launch_bounds__(256)
     if (j >> l & 1) jb |= uint64_t(1) << args.qorder[l];
   const uint64_t cnt = uint64_t(1) << args.slice_bits;
   const uint64_t r0 = sl << args.slice_bits;
+  // Spreading the rest index over the non-marginal qubits distributes over
+  // OR of disjoint bit sets: spread(r0 | k | t) = spread(r0) | spread(k) |
+  // spread(t) for the slice base r0, the step k (multiple of 256) and the
+  // thread offset t < 256, so only the uniform step term changes per step.
+  auto spread = [&](uint64_t x) {
+    for (int l = 0; l < args.m; ++l) x = insert_zero64(x, args.qsorted[l]);
+    return x;
+  };
+  const uint64_t fixed = spread(r0) | spread(threadIdx.x) | jb;
+  // spread(k) for k = 0, 256, 512, ... enumerates the subsets of the mask
+  // mk in increasing order: next = ((x | ~mk) + 1) & mk.
+  const uint64_t mk = cnt > 256 ? spread(cnt - 1) & ~spread(255) : 0;
   double s = 0, c = 0;
-  for (uint64_t r = threadIdx.x; r < cnt; r += 256) {
-    uint64_t i = r0 + r;
-    for (int l = 0; l < args.m; ++l) i = insert_zero64(i, args.qsorted[l]);
-    nadd(s, c, prob_of(a[i | jb]));
+  if (threadIdx.x < cnt) {
+    uint64_t x = 0;
+    do {
+      nadd(s, c, prob_of(a[fixed | x]));
+      x = ((x | ~mk) + 1) & mk;
+    } while (x != 0);
   }
   block_reduce_pair(s, c, sh);
   if (threadIdx.x == 0) {
@@ -281,19 +295,58 @@ struct FromProbs {
   static __device__ __forceinline__ double p(P v) { return double(v); }
 };
 
+// Wave-local ordering of LDS writes before reads by other lanes.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS slice of one wave: 1024 doubles plus one pad per 16 (bank spread).
+constexpr int kWaveSlice = 1024 + 64;
+__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
+
+// Probabilities of block `blk` (2^B amplitudes) as lane `lane` sees them:
+// p[e] = p(amplitude lane * E + e), e < E, with E = 2^B / min(2^B, 64).  For
+// full 1024-amplitude blocks the wave reads the block with coalesced loads
+// (lane l takes amplitudes l, l + 64, ...) and redistributes it through its
+// LDS slice, so every lane ends with its 16 consecutive probabilities.
+template <class Acc>
+__device__ __forceinline__ void block_probs(
+    const typename Acc::in_t* __restrict__ a, uint64_t blk, int B, int lane,
+    double* __restrict__ sl, double (&p)[16]) {
+  const uint64_t base = blk << B;
+  if (B == 10) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      sl[pad16(e * 64 + lane)] = Acc::p(a[base + uint64_t(e) * 64 + lane]);
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) p[e] = sl[pad16(lane * 16 + e)];
+    wave_sync();  // the slice may be rewritten by the caller's next block
+    return;
+  }
+  const int lanes = (1 << B) < 64 ? (1 << B) : 64;
+  const int E = (1 << B) / lanes;
+#pragma unroll
+  for (int e = 0; e < 16; ++e)
+    p[e] = (lane < lanes && e < E) ? Acc::p(a[base + uint64_t(lane) * E + e])
+                                   : 0.0;
+}
+
 template <class Acc>
 __global__ void __launch_bounds__(256)
     sample_blocksum_kernel(const typename Acc::in_t* __restrict__ a, int B,
                            uint64_t nblocks, double* __restrict__ S) {
+  __shared__ double sh[4 * kWaveSlice];
   const uint64_t w = uint64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (w >= nblocks) return;  // whole waves exit together
-  const int lanes = (1 << B) < 64 ? (1 << B) : 64;
-  const int E = (1 << B) / lanes;
+  double p[16];
+  block_probs<Acc>(a, w, B, lane, sh + (threadIdx.x >> 6) * kWaveSlice, p);
   double loc = 0;
-  if (lane < lanes)
-    for (int e = 0; e < E; ++e)
-      loc += Acc::p(a[(w << B) + uint64_t(lane) * E + e]);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) loc += p[e];
   const double incl = wave_incl_scan(loc);
   if (lane == 63) S[w] = incl;
 }
@@ -367,6 +420,7 @@ __global__ void __launch_bounds__(256)
     sample_kernel(const typename Acc::in_t* __restrict__ a, int B,
                   uint64_t nblocks, const double* __restrict__ P,
                   uint64_t shots, uint64_t seed, uint64_t* __restrict__ out) {
+  __shared__ double sh[4 * kWaveSlice];
   const uint64_t j = uint64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (j >= shots) return;  // whole waves exit together
@@ -385,15 +439,10 @@ __global__ void __launch_bounds__(256)
   const int lanes = (1 << B) < 64 ? (1 << B) : 64;
   const int E = (1 << B) / lanes;
   double p[16];
+  block_probs<Acc>(a, b, B, lane, sh + (threadIdx.x >> 6) * kWaveSlice, p);
   double loc = 0;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    p[e] = 0.0;
-    if (lane < lanes && e < E) {
-      p[e] = Acc::p(a[(b << B) + uint64_t(lane) * E + e]);
-      loc += p[e];
-    }
-  }
+  for (int e = 0; e < 16; ++e) loc += p[e];
   const double incl = wave_incl_scan(loc);
   double excl = __shfl_up(incl, 1, 64);
   if (lane == 0) excl = 0.0;

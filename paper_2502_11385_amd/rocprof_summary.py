@@ -18,6 +18,15 @@ import sqlite3
 import sys
 
 
+def sources_hash(paths) -> str:
+    """First 16 hex digits of the SHA-256 over the files' bytes, in order."""
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def _rows(db: str, sql: str):
     c = sqlite3.connect(db)
     try:
@@ -88,8 +97,8 @@ def main() -> int:
     t.add_argument("--kernel", default="tile_kernel")
     t.add_argument("--copy-bytes", type=int, default=1 << 30)
     t.add_argument("--json", default=None)
-    t.add_argument("--source", default=None,
-                   help="kernel source file whose hash is recorded")
+    t.add_argument("--source", default=None, nargs="+",
+                   help="kernel source files whose combined hash is recorded")
     t.add_argument("--strategy", default="tiled")
     a = ap.parse_args()
     if a.cmd == "stats":
@@ -99,8 +108,7 @@ def main() -> int:
         return 0
     r = traffic(a.fetch_db, a.write_db, a.kernel, a.copy_bytes)
     if a.source:
-        with open(a.source, "rb") as f:
-            r["kernel_source_sha256_16"] = hashlib.sha256(f.read()).hexdigest()[:16]
+        r["kernel_source_sha256_16"] = sources_hash(a.source)
         r["strategy"] = a.strategy
     print(json.dumps(r, indent=1))
     if a.json:
