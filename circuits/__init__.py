@@ -10,6 +10,10 @@ records, which is the only thing they share.
 from .generators import (  # noqa: F401
     Gate,
     BatchCircuit,
+    CutSub,
+    CutProblem,
+    cut_chain,
+    cut_variants,
     ServeRequest,
     layered_circuit,
     ghz_circuit,

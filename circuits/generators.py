@@ -243,3 +243,116 @@ def serve_trace(n_requests: int = 2000, rate_per_s: float = 100.0,
         cs = int(rng.integers(0, 1 << 62))
         out.append(ServeRequest(t, w, d, prec, samp, shots, cs))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Wire-cut problems (Section III.A): an uncut circuit made of subcircuits in a
+# chain, consecutive subcircuits sharing one wire that is cut between them.
+
+
+@dataclass
+class CutSub:
+    """One subcircuit of a cut problem, in its local qubit numbering.
+
+    Per local qubit j: ``out_qubit[j]`` is the uncut qubit whose final value
+    is measured at j (-1: none), ``cut_in[j]`` the cut whose downstream end
+    initialises j (-1: none), ``cut_out[j]`` the cut whose upstream end is
+    measured at j (-1: none).  Every local qubit is measured exactly once:
+    as an output or as a cut's upstream end.
+    """
+    width: int
+    depth: int
+    gates: List[Gate]
+    out_qubit: List[int]
+    cut_in: List[int]
+    cut_out: List[int]
+
+
+@dataclass
+class CutProblem:
+    n: int                 # qubits of the uncut circuit
+    n_cuts: int
+    subs: List[CutSub]
+    uncut: List[Gate]      # the same circuit without cuts, on n qubits
+
+
+def cut_chain(widths: Sequence[int], depth: int, seed: int) -> CutProblem:
+    """Chain of len(widths) subcircuits cut on len(widths) - 1 wires.
+
+    Subcircuit s has its own qubits; for s > 0 its local qubit 0 is the wire
+    coming from subcircuit s - 1 (cut s - 1, downstream end, measured at the
+    end as that wire's uncut qubit), and for s < S - 1 its local qubit
+    w_s - 1 is the wire going to subcircuit s + 1 (cut s, upstream end).  A
+    middle subcircuit of width 1 is one wire cut on both sides: initialised
+    by cut s - 1 and measured for cut s, with no output.  Uncut qubits are
+    numbered in order of first appearance.  Bodies are drawn one after the
+    other from one generator: per subcircuit, ``depth`` U3 layers with a
+    CZ/CNOT brick wall (coin per pair).  The uncut circuit is the bodies in
+    subcircuit order on the uncut qubits.
+    """
+    rng = _rng(seed)
+    S = len(widths)
+    subs: List[CutSub] = []
+    uncut: List[Gate] = []
+    nxt = 0
+    wire_q = -1
+    for s, w in enumerate(widths):
+        if w < 1 or (S > 1 and w < 2 and s in (0, S - 1)):
+            raise ValueError("end subcircuits of a chain need width >= 2")
+        out_q, c_in, c_out, umap = [], [], [], []
+        for j in range(w):
+            if w == 1 and 0 < s < S - 1:       # a wire cut on both sides
+                out_q.append(-1); c_in.append(s - 1); c_out.append(s)
+                umap.append(wire_q)
+            elif s > 0 and j == 0:             # incoming wire
+                out_q.append(wire_q); c_in.append(s - 1); c_out.append(-1)
+                umap.append(wire_q)
+            elif s < S - 1 and j == w - 1:     # outgoing wire
+                out_q.append(-1); c_in.append(-1); c_out.append(s)
+                umap.append(nxt)
+                wire_q = nxt
+                nxt += 1
+            else:
+                out_q.append(nxt); c_in.append(-1); c_out.append(-1)
+                umap.append(nxt)
+                nxt += 1
+        body = _layers(rng, w, depth, "mixed")
+        subs.append(CutSub(w, depth, body, out_q, c_in, c_out))
+        uncut += [Gate(g.name, tuple(umap[q] for q in g.qubits), g.params)
+                  for g in body]
+    return CutProblem(nxt, S - 1, subs, uncut)
+
+
+def cut_variants(sub: CutSub) -> List[BatchCircuit]:
+    """All variants of one subcircuit in the canonical order.
+
+    The subcircuit's cut ends, in increasing local qubit order, are the
+    digits of the variant index, the first end least significant: a
+    downstream end (cut input) has 4 values, labels 0, 1, +, +i; an
+    upstream end (cut output) has 3, bases I, X, Y.  A qubit that is both
+    contributes its input digit first.
+    """
+    ends = []
+    for j in range(sub.width):
+        if sub.cut_in[j] >= 0:
+            ends.append(("in", j))
+        if sub.cut_out[j] >= 0:
+            ends.append(("out", j))
+    total = 1
+    for kind, _ in ends:
+        total *= 4 if kind == "in" else 3
+    out = []
+    for v in range(total):
+        r = v
+        ins, outs = [], []
+        for kind, j in ends:
+            if kind == "in":
+                ins.append((j, INIT_LABELS[r % 4]))
+                r //= 4
+            else:
+                outs.append((j, BASIS_LABELS[r % 3]))
+                r //= 3
+        out.append(BatchCircuit(sub.width, sub.depth, list(sub.gates), ins,
+                                outs))
+    return out
+

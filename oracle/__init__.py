@@ -24,5 +24,7 @@ from .statevector import (  # noqa: F401
     cut_prologue,
     cut_epilogue,
     variant_probabilities,
+    cut_term_vectors,
+    cut_reconstruct,
     state_bytes,
 )

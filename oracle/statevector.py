@@ -308,6 +308,111 @@ def variant_probabilities(circ) -> np.ndarray:
     return probabilities(simulate(circ.width, gates))
 
 
+def cut_term_vectors(sub, variant_probs) -> dict:
+    """The per-term vectors of one subcircuit (Section III.A).
+
+    ``variant_probs[v]`` is the probability vector of variant v in the
+    canonical order of ``circuits.cut_variants``.  A term assigns each of the
+    subcircuit's cut ends one of the four indices i = 1..4 of the one-cut
+    identity (written 0..3 here):
+
+    * downstream end (the cut's initialised qubit): p_{2,1} = p(|0>),
+      p_{2,2} = p(|1>), p_{2,3} = 2 p(|+>) - p(|0>) - p(|1>),
+      p_{2,4} = 2 p(|+i>) - p(|0>) - p(|1>)  (eqs 3.3-3.6);
+    * upstream end (the cut's measured qubit), by shot attribution (eq 3.7):
+      p_{1,1} = I + Z and p_{1,2} = I - Z from the I-basis readout, p_{1,3}
+      = X and p_{1,4} = Y from the X and Y readouts, where I sums both
+      outcomes and Z, X, Y weigh outcome 1 by -1.
+
+    Returns {term tuple over the ends (canonical end order): vector over the
+    subcircuit's output qubits, bit i = i-th output qubit in local order}.
+    """
+    import itertools
+    w = sub.width
+    ends = []
+    for j in range(w):
+        if sub.cut_in[j] >= 0:
+            ends.append(("in", j))
+        if sub.cut_out[j] >= 0:
+            ends.append(("out", j))
+    radix = [4 if k == "in" else 3 for k, _ in ends]
+    outs = [j for j in range(w) if sub.out_qubit[j] >= 0]
+    init_mix = {0: [(0, 1.0)], 1: [(1, 1.0)],
+                2: [(2, 2.0), (0, -1.0), (1, -1.0)],
+                3: [(3, 2.0), (0, -1.0), (1, -1.0)]}
+    basis_of = {0: 0, 1: 0, 2: 1, 3: 2}             # I, I, X, Y
+    weight = {0: (2.0, 0.0), 1: (0.0, 2.0), 2: (1.0, -1.0), 3: (1.0, -1.0)}
+    result = {}
+    for t in itertools.product(range(4), repeat=len(ends)):
+        # expand the initialisation mixtures into (variant digits, coef)
+        choices = []
+        for (kind, j), ti in zip(ends, t):
+            choices.append(init_mix[ti] if kind == "in"
+                           else [(basis_of[ti], 1.0)])
+        acc = np.zeros(1 << len(outs))
+        for combo in itertools.product(*choices):
+            v, mult, coef = 0, 1, 1.0
+            for (digit, c), r in zip(combo, radix):
+                v += digit * mult
+                mult *= r
+                coef *= c
+            # (2,)*w tensor, axis w-1-j <-> local qubit j
+            tens = np.asarray(variant_probs[v], dtype=np.float64).reshape(
+                (2,) * w)
+            for (kind, j), ti in zip(ends, t):
+                if kind == "out":
+                    wv = np.zeros((2,) * w)
+                    sl0 = [slice(None)] * w
+                    sl1 = [slice(None)] * w
+                    sl0[w - 1 - j] = 0
+                    sl1[w - 1 - j] = 1
+                    wv[tuple(sl0)] = weight[ti][0]
+                    wv[tuple(sl1)] = weight[ti][1]
+                    tens = tens * wv
+            # sum out the measured cut qubits, keep outputs
+            summed = [w - 1 - j for kind, j in ends if kind == "out"]
+            red = tens.sum(axis=tuple(summed)) if summed else tens
+            # remaining axes are the outputs in descending local order
+            acc += coef * red.reshape(-1)
+        result[t] = acc
+    return result
+
+
+def cut_reconstruct(problem, variant_probs) -> np.ndarray:
+    """Probability vector of the uncut circuit from its subcircuits' variants.
+
+    p(x) = (1/2)^K sum over term assignments (i_1..i_K) of the product over
+    subcircuits of their term vectors at x's bits (Section III.A, the one-cut
+    rule applied to every cut).  ``variant_probs[s][v]`` as in
+    ``cut_term_vectors``.
+    """
+    import itertools
+    n, K = problem.n, problem.n_cuts
+    x = np.arange(1 << n, dtype=np.int64)
+    per_sub = []
+    for s, sub in enumerate(problem.subs):
+        terms = cut_term_vectors(sub, variant_probs[s])
+        ends = []
+        for j in range(sub.width):
+            if sub.cut_in[j] >= 0:
+                ends.append(sub.cut_in[j])
+            if sub.cut_out[j] >= 0:
+                ends.append(sub.cut_out[j])
+        outs = [sub.out_qubit[j] for j in range(sub.width)
+                if sub.out_qubit[j] >= 0]
+        y = np.zeros_like(x)
+        for i, q in enumerate(outs):
+            y |= ((x >> q) & 1) << i
+        per_sub.append((ends, terms, y))
+    p = np.zeros(1 << n)
+    for tk in itertools.product(range(4), repeat=K):
+        prod = np.ones(1 << n)
+        for ends, terms, y in per_sub:
+            prod = prod * terms[tuple(tk[c] for c in ends)][y]
+        p += prod
+    return p * 0.5 ** K
+
+
 # ---------------------------------------------------------------------------
 
 

@@ -64,3 +64,24 @@ def test_serve_trace():
     frac64 = np.mean([r.precision == "c64" for r in tr])
     assert 0.7 < frac64 < 0.9
     assert all(8 <= r.width <= 28 and 10 <= r.depth <= 100 for r in tr)
+
+
+def test_cut_chain_structure():
+    from circuits import cut_chain, cut_variants
+    prob = cut_chain((3, 4, 1, 3), 2, 9)
+    # each cut joins two ends of one uncut qubit
+    assert prob.n_cuts == 3 and prob.n == (3 + 4 + 1 + 3) - 3
+    ins = [c for sub in prob.subs for c in sub.cut_in if c >= 0]
+    outs = [c for sub in prob.subs for c in sub.cut_out if c >= 0]
+    assert sorted(ins) == sorted(outs) == [0, 1, 2]
+    outq = sorted(q for sub in prob.subs for q in sub.out_qubit if q >= 0)
+    assert outq == list(range(prob.n))
+    for sub in prob.subs:               # every local qubit measured once
+        for j in range(sub.width):
+            assert (sub.out_qubit[j] >= 0) != (sub.cut_out[j] >= 0)
+    counts = [len(cut_variants(sub)) for sub in prob.subs]
+    assert counts == [3, 12, 12, 4]
+    v = cut_variants(prob.subs[1])
+    # first end (local 0, input) is the least significant digit
+    assert v[1].cut_inputs == [(0, "1")] and v[4].cut_outputs == [(3, "X")]
+

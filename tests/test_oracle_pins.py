@@ -351,6 +351,37 @@ def test_cut_reconstruction_identity():
     assert np.max(np.abs(rebuilt - p_full)) < 1e-14
 
 
+@pytest.mark.parametrize("widths,depth,seed", [
+    ((3, 3), 3, 11), ((3, 4, 3), 3, 12), ((2, 3, 3, 2), 2, 13),
+    ((3, 1, 3), 2, 14), ((2, 1, 1, 3), 2, 15), ((5,), 4, 16)])
+def test_cut_chain_reconstruction_matches_uncut(widths, depth, seed):
+    """The multi-cut rebuild (every cut by the one-cut rule) from oracle
+    variant vectors equals the uncut circuit's distribution."""
+    from circuits import cut_chain, cut_variants
+    prob = cut_chain(widths, depth, seed)
+    vp = [[oracle.variant_probabilities(v) for v in cut_variants(sub)]
+          for sub in prob.subs]
+    rec = oracle.cut_reconstruct(prob, vp)
+    full = oracle.probabilities(oracle.simulate(prob.n, prob.uncut))
+    assert np.max(np.abs(rec - full)) < 1e-13
+
+
+def test_cut_reconstruction_detects_wrong_variant():
+    """Swapping the X- and Y-basis variants of the upstream subcircuit (or
+    dropping the X/Y terms) breaks the rebuild."""
+    from circuits import cut_chain, cut_variants
+    prob = cut_chain((3, 3), 3, 21)
+    vp = [[oracle.variant_probabilities(v) for v in cut_variants(sub)]
+          for sub in prob.subs]
+    full = oracle.probabilities(oracle.simulate(prob.n, prob.uncut))
+    bad = [list(vp[0]), vp[1]]
+    bad[0][1], bad[0][2] = vp[0][2], vp[0][1]     # X <-> Y readout
+    assert np.max(np.abs(oracle.cut_reconstruct(prob, bad) - full)) > 1e-3
+    flat = [list(vp[0]), vp[1]]
+    flat[0][1] = flat[0][2] = np.full_like(vp[0][1], 0.25)  # no X/Y signal
+    assert np.max(np.abs(oracle.cut_reconstruct(prob, flat) - full)) > 1e-3
+
+
 # --------------------------------------------------------------------------
 # Table III
 
