@@ -388,6 +388,67 @@ qsv_status qsv_server_destroy(qsv_server s);
 /* The library's steady clock, in seconds. */
 double qsv_clock(void);
 
+/* ---------------------------------------------------- cut reconstruction */
+
+/* A wire-cut problem (Section III.A): n_sub subcircuits joined by n_cuts
+ * cut wires.  Subcircuit s has widths[s] local qubits; for each local qubit
+ * (arrays concatenated over s, sum of widths entries each):
+ *   out_qubit : the uncut qubit whose final value is measured there, or -1
+ *   cut_in    : the cut whose downstream end initialises it, or -1
+ *   cut_out   : the cut whose upstream end is measured there, or -1
+ * Every local qubit is measured exactly once (out_qubit >= 0 or
+ * cut_out >= 0, not both); every cut has one upstream and one downstream end
+ * in two different subcircuits; every uncut qubit 0..n_qubits-1 is the
+ * out_qubit of exactly one local qubit.
+ *
+ * Variants of subcircuit s are numbered by its cut ends taken in increasing
+ * local-qubit order (a downstream end before an upstream end on the same
+ * qubit), the first end least significant: a downstream end is a digit in
+ * 0..3 (initial state |0>, |1>, |+>, |+i>), an upstream end a digit in 0..2
+ * (readout basis I, X, Y; X is read after H, Y after S-dagger then H).
+ * This is the order of the prologue / epilogue labels of qsv_variant.
+ *
+ * Limits: 1 <= n_sub <= 16, 0 <= n_cuts <= 8, widths 1..24, at most 6 cut
+ * ends per subcircuit, 1 <= n_qubits <= 30. */
+typedef struct {
+  int32_t n_sub;
+  int32_t n_cuts;
+  int32_t n_qubits;
+  const int32_t* widths;
+  const int32_t* out_qubit;
+  const int32_t* cut_in;
+  const int32_t* cut_out;
+} qsv_cut_spec;
+
+/* Device workspace that qsv_cut_reconstruct needs for this problem.
+ * Validates the specification (QSV_ERR_INVALID_ARG with a message). */
+qsv_status qsv_cut_workspace_bytes(const qsv_cut_spec* spec, uint64_t* bytes);
+
+/* Probability vector of the uncut circuit from its subcircuits' variant
+ * probability vectors (Section III.A: per subcircuit, the four terms of
+ * every cut end, by shot attribution (eq 3.7) for upstream ends and by the
+ * initial-state combinations of eqs 3.3-3.6 for downstream ends; then
+ * p(x) = (1/2)^K times the sum over all 4^K term choices of the product over
+ * subcircuits of their term vectors at x's bits).
+ *   probs_dev  : device buffer of probs_elems FP32 (probs_fp64 = 0) or FP64
+ *                entries holding every variant's 2^w vector (little-endian
+ *                index, as written by qsv_batch_launch or qsv_probabilities)
+ *   offsets    : host, for s = 0..n_sub-1 and each variant v of s in the
+ *                order above: the element offset of its vector in probs_dev;
+ *                each vector must lie inside probs_elems
+ *   workspace  : device, at least qsv_cut_workspace_bytes; owned by the
+ *                caller and not used by anything else until the work is done
+ *   out_dev    : device, 2^n_qubits FP64, written (bit q of the index =
+ *                uncut qubit q)
+ * All arithmetic is FP64.  The call validates everything on the host first
+ * (nothing is launched on an error), copies its tables into the workspace on
+ * the stream, waits for that copy, then enqueues two kernels and returns. */
+qsv_status qsv_cut_reconstruct(const qsv_cut_spec* spec, const void* probs_dev,
+                               int32_t probs_fp64, uint64_t probs_elems,
+                               const uint64_t* offsets, void* workspace,
+                               uint64_t workspace_bytes, double* out_dev,
+                               void* hip_stream);
+
 /* ---------------------------------------------------- copies and control */
 
 /* Copy all amplitudes to / from host memory (2^n interleaved pairs of the

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build", "qsv")
 LIB = os.path.join(HERE, "libqsv.so")
 
-SOURCES = ["api.cpp", "planner.cpp", "batch.cpp", "server.cpp", "k_gate.hip",
+SOURCES = ["api.cpp", "planner.cpp", "batch.cpp", "server.cpp", "cut.cpp",
+           "k_gate.hip", "k_cut.hip",
            "k_tile.hip", "k_reduce.hip", "k_fused.hip", "k_batch.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

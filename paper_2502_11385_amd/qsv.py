@@ -51,6 +51,7 @@ EXPORTED = [
     "qsv_server_create", "qsv_server_submit", "qsv_server_wait",
     "qsv_server_release", "qsv_server_stats", "qsv_server_destroy",
     "qsv_clock", "qsv_debug_emulate_tiled",
+    "qsv_cut_workspace_bytes", "qsv_cut_reconstruct",
 ]
 
 
@@ -100,6 +101,15 @@ class qsv_request(C.Structure):
     _fields_ = [("width", C.c_int32), ("prec", C.c_int32),
                 ("body", qsv_circuit), ("want_samples", C.c_int32),
                 ("shots", C.c_uint64), ("seed", C.c_uint64)]
+
+
+class qsv_cut_spec(C.Structure):
+    _fields_ = [("n_sub", C.c_int32), ("n_cuts", C.c_int32),
+                ("n_qubits", C.c_int32),
+                ("widths", C.POINTER(C.c_int32)),
+                ("out_qubit", C.POINTER(C.c_int32)),
+                ("cut_in", C.POINTER(C.c_int32)),
+                ("cut_out", C.POINTER(C.c_int32))]
 
 
 class qsv_result(C.Structure):
@@ -156,6 +166,9 @@ _SIGS = {
     "qsv_server_stats": [_p, _pu64, _i32],
     "qsv_server_destroy": [_p],
     "qsv_pass_times": [_p, C.POINTER(C.c_float), _pi32, _i32, _pi32],
+    "qsv_cut_workspace_bytes": [C.POINTER(qsv_cut_spec), _pu64],
+    "qsv_cut_reconstruct": [C.POINTER(qsv_cut_spec), _p, _i32, _u64, _pu64,
+                            _p, _u64, _p, _p],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -542,6 +555,50 @@ class Batch:
                 _lib.qsv_batch_free(self._h)
         except Exception:
             pass
+
+
+# ------------------------------------------------------ cut reconstruction
+
+class CutSpec:
+    """A wire-cut problem for ``qsv_cut_reconstruct``.
+
+    ``subs`` are records with ``width`` and per-local-qubit lists
+    ``out_qubit``, ``cut_in``, ``cut_out`` (e.g. ``circuits.CutSub``)."""
+
+    def __init__(self, n_qubits: int, n_cuts: int, subs):
+        self.n_qubits, self.n_cuts, self.n_sub = n_qubits, n_cuts, len(subs)
+        self._w = np.asarray([sb.width for sb in subs], np.int32)
+        self._oq = np.asarray([q for sb in subs for q in sb.out_qubit], np.int32)
+        self._ci = np.asarray([c for sb in subs for c in sb.cut_in], np.int32)
+        self._co = np.asarray([c for sb in subs for c in sb.cut_out], np.int32)
+        self._s = qsv_cut_spec(self.n_sub, n_cuts, n_qubits,
+                               _ptr(self._w, C.c_int32),
+                               _ptr(self._oq, C.c_int32),
+                               _ptr(self._ci, C.c_int32),
+                               _ptr(self._co, C.c_int32))
+
+    def workspace_bytes(self) -> int:
+        out = C.c_uint64()
+        _check(_lib.qsv_cut_workspace_bytes(C.byref(self._s), C.byref(out)))
+        return int(out.value)
+
+
+def cut_reconstruct(spec: CutSpec, probs, offsets, out, workspace=None,
+                    stream=None) -> None:
+    """Uncut probability vector (FP64 device tensor ``out``, 2^n entries)
+    from the variant vectors in the device tensor ``probs`` (float32 or
+    float64) at element ``offsets`` (subcircuit-major, canonical variant
+    order)."""
+    import torch
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    if workspace is None:
+        workspace = torch.empty(max(1, spec.workspace_bytes()),
+                                dtype=torch.uint8, device=probs.device)
+    fp64 = 1 if probs.dtype == torch.float64 else 0
+    _check(_lib.qsv_cut_reconstruct(
+        C.byref(spec._s), probs.data_ptr(), fp64, probs.numel(),
+        _ptr(off, C.c_uint64), workspace.data_ptr(), workspace.numel(),
+        out.data_ptr(), _stream_handle(stream)))
 
 
 # ---------------------------------------------------------------- serving
