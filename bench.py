@@ -96,6 +96,57 @@ PROLOGUE = {"0": [], "1": ["x"], "+": ["h"], "+i": ["h", "s"]}
 EPILOGUE = {"I": [], "X": ["h"], "Y": ["sdg", "h"]}
 
 
+CUT_WIDTHS, CUT_DEPTH, CUT_SEED = (10, 12, 10), 20, 30
+
+
+def cut_leg(qsv, torch, np, steps: int) -> dict:
+    """Cutting end to end at 30 uncut qubits: a chain of three subcircuits
+    (10, 12, 10 qubits, two cut wires, depth 20), all 19 variants in one
+    batch launch (complex64, FP32 outputs), then the reconstruction of the
+    2^30-entry FP64 distribution on the device."""
+    from circuits import cut_chain, cut_variants
+    prob = cut_chain(CUT_WIDTHS, CUT_DEPTH, CUT_SEED)
+    variants = [v for sub in prob.subs for v in cut_variants(sub)]
+    b = qsv.Batch(variants, prec=qsv.QSV_C64)
+    vout = b.output()
+    spec = qsv.CutSpec(prob.n, prob.n_cuts, prob.subs)
+    ws = torch.empty(spec.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    rec = torch.empty(1 << prob.n, dtype=torch.float64, device="cuda")
+    offs = b.offsets[:-1].copy()
+    b.launch(vout)
+    qsv.cut_reconstruct(spec, vout, offs, rec, ws)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_var = t_rec = 0.0
+    for _ in range(steps):
+        e[0].record()
+        b.launch(vout)
+        e[1].record()
+        qsv.cut_reconstruct(spec, vout, offs, rec, ws)
+        e[2].record()
+        torch.cuda.synchronize()
+        t_var += e[0].elapsed_time(e[1])
+        t_rec += e[1].elapsed_time(e[2])
+    t_var /= steps
+    t_rec /= steps
+    total = float(rec.sum().item())
+    b.free()
+    out_bytes = 8 << prob.n
+    res = {"workload": (f"cut chain of {len(CUT_WIDTHS)} subcircuits "
+                        f"{CUT_WIDTHS}, {prob.n_cuts} cuts, depth {CUT_DEPTH}, "
+                        f"seed {CUT_SEED}: {len(variants)} variants (c64) -> "
+                        f"2^{prob.n} FP64 probabilities"),
+           "variants_ms": round(t_var, 3),
+           "reconstruct_ms": round(t_rec, 3),
+           "reconstruct_output_GBps": round(out_bytes / (t_rec * 1e-3) / 1e9,
+                                            1),
+           "terms_per_output": 4 ** prob.n_cuts,
+           "sum_p": total}
+    del rec, vout, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def batch_leg(qsv, torch, np, steps: int, per_circuit: bool) -> dict:
     """4096 cut variants (widths 10..20, depths 10..60), complex64: one
     persistent launch (autotuned, replayed from a hipGraph) against one
@@ -262,6 +313,8 @@ def main() -> int:
                     help="skip the batched cut-variant leg")
     ap.add_argument("--no-per-circuit", action="store_true",
                     help="skip the one-call-per-circuit batch baseline")
+    ap.add_argument("--no-cut", action="store_true",
+                    help="skip the cut-and-reconstruct leg")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the request-serving leg")
     ap.add_argument("--serve-n", type=int, default=300,
@@ -410,6 +463,8 @@ def main() -> int:
     state.free()
     del probs
     torch.cuda.empty_cache()
+    if not a.no_cut:
+        out["cut"] = cut_leg(qsv, torch, np, max(1, a.steps))
     if not a.no_batch:
         out["batch"] = batch_leg(qsv, torch, np, max(1, a.steps),
                                  not a.no_per_circuit)

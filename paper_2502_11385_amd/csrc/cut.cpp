@@ -25,6 +25,9 @@ struct CutPlan {
   std::vector<uint64_t> n_variants;   // per subcircuit
   std::vector<uint64_t> tt;           // [4^K][n_sub]
   std::vector<std::vector<int>> end_cut;  // per subcircuit, cut of each end
+  std::vector<int> vary, uni;         // wave-kernel split of subcircuits
+  std::vector<uint64_t> ttv, ttu;     // its term-vector start tables
+  uint64_t n_c = 1, n_u = 1, o_ttv = 0, o_ttu = 0;
   uint64_t total_variants = 0, total_entries = 0, n_terms = 1;
   uint64_t o_voff = 0, o_tt = 0, o_T = 0, bytes = 0;
 };
@@ -91,6 +94,20 @@ std::string plan_cut(const qsv_cut_spec* sp, CutPlan* P) {
   }
   for (int q = 0; q < n; ++q)
     if (!seen_q[q]) return "an uncut qubit is never measured";
+  for (int s = 0; s < S; ++s) {  // outputs as runs of consecutive uncut qubits
+    CutSubDev& d = P->subs[s];
+    for (int i = 0; i < d.eff; ++i) {
+      if (d.n_runs > 0 && d.out_uncut[i] == d.run_src[d.n_runs - 1] +
+                                                 d.run_len[d.n_runs - 1]) {
+        ++d.run_len[d.n_runs - 1];
+        continue;
+      }
+      d.run_src[d.n_runs] = d.out_uncut[i];
+      d.run_dst[d.n_runs] = i;
+      d.run_len[d.n_runs] = 1;
+      ++d.n_runs;
+    }
+  }
   for (int k = 0; k < K; ++k) {
     if (seen_in[k] < 0 || seen_out[k] < 0)
       return "every cut needs one upstream and one downstream end";
@@ -114,17 +131,53 @@ std::string plan_cut(const qsv_cut_spec* sp, CutPlan* P) {
   P->total_entries = ent;
   P->total_variants = voff;
   P->tt.assign(P->n_terms * uint64_t(S), 0);
+  auto term_start = [&](int s, uint64_t t) {
+    const CutSubDev& d = P->subs[s];
+    uint64_t ti = 0;
+    for (int e = 0; e < d.n_ends; ++e)
+      ti |= ((t >> (2 * P->end_cut[s][e])) & 3) << (2 * e);
+    return d.t_offset + (ti << d.eff);
+  };
   for (uint64_t t = 0; t < P->n_terms; ++t)
-    for (int s = 0; s < S; ++s) {
-      const CutSubDev& d = P->subs[s];
-      uint64_t ti = 0;
-      for (int e = 0; e < d.n_ends; ++e)
-        ti |= ((t >> (2 * P->end_cut[s][e])) & 3) << (2 * e);
-      P->tt[t * S + s] = d.t_offset + (ti << d.eff);
-    }
+    for (int s = 0; s < S; ++s) P->tt[t * S + s] = term_start(s, t);
+  // wave kernel split: subcircuits with an output among uncut qubits 0..5
+  // vary across a wave's lanes; cuts touching them index c, the rest u
+  P->vary.clear();
+  P->uni.clear();
+  std::vector<int> cut_vary(K, 0);
+  for (int s = 0; s < S; ++s) {
+    const CutSubDev& d = P->subs[s];
+    bool vary = false;
+    for (int i = 0; i < d.eff; ++i) vary = vary || d.out_uncut[i] < 6;
+    (vary ? P->vary : P->uni).push_back(s);
+    if (vary)
+      for (int k : P->end_cut[s]) cut_vary[k] = 1;
+  }
+  std::vector<int> cv, cu;
+  for (int k = 0; k < K; ++k) (cut_vary[k] ? cv : cu).push_back(k);
+  P->n_c = uint64_t(1) << (2 * cv.size());
+  P->n_u = uint64_t(1) << (2 * cu.size());
+  auto compose = [&](uint64_t c, uint64_t u) {
+    uint64_t t = 0;
+    for (size_t i = 0; i < cv.size(); ++i) t |= ((c >> (2 * i)) & 3) << (2 * cv[i]);
+    for (size_t i = 0; i < cu.size(); ++i) t |= ((u >> (2 * i)) & 3) << (2 * cu[i]);
+    return t;
+  };
+  P->ttv.assign(P->n_c * P->vary.size(), 0);
+  P->ttu.assign(P->n_c * P->n_u * P->uni.size(), 0);
+  for (uint64_t c = 0; c < P->n_c; ++c) {
+    for (size_t k = 0; k < P->vary.size(); ++k)
+      P->ttv[c * P->vary.size() + k] = term_start(P->vary[k], compose(c, 0));
+    for (uint64_t u = 0; u < P->n_u; ++u)
+      for (size_t k = 0; k < P->uni.size(); ++k)
+        P->ttu[(c * P->n_u + u) * P->uni.size() + k] =
+            term_start(P->uni[k], compose(c, u));
+  }
   P->o_voff = align256(sizeof(CutSubDev) * S);
   P->o_tt = P->o_voff + align256(8 * P->total_variants);
-  P->o_T = P->o_tt + align256(8 * P->tt.size());
+  P->o_ttv = P->o_tt + align256(8 * P->tt.size());
+  P->o_ttu = P->o_ttv + align256(8 * P->ttv.size());
+  P->o_T = P->o_ttu + align256(8 * P->ttu.size());
   P->bytes = P->o_T + align256(8 * P->total_entries);
   return "";
 }
@@ -173,6 +226,8 @@ qsv_status qsv_cut_reconstruct(const qsv_cut_spec* spec, const void* probs_dev,
   std::memcpy(host.data(), P.subs.data(), sizeof(CutSubDev) * P.subs.size());
   std::memcpy(host.data() + P.o_voff, offsets, 8 * P.total_variants);
   std::memcpy(host.data() + P.o_tt, P.tt.data(), 8 * P.tt.size());
+  std::memcpy(host.data() + P.o_ttv, P.ttv.data(), 8 * P.ttv.size());
+  std::memcpy(host.data() + P.o_ttu, P.ttu.data(), 8 * P.ttu.size());
   char* ws = static_cast<char*>(workspace);
   hipError_t he = hipMemcpyAsync(ws, host.data(), host.size(),
                                  hipMemcpyHostToDevice, stream);
@@ -191,6 +246,14 @@ qsv_status qsv_cut_reconstruct(const qsv_cut_spec* spec, const void* probs_dev,
   a.tt = reinterpret_cast<const uint64_t*>(ws + P.o_tt);
   a.T = reinterpret_cast<double*>(ws + P.o_T);
   a.probs = probs_dev;
+  a.ttv = reinterpret_cast<const uint64_t*>(ws + P.o_ttv);
+  a.ttu = reinterpret_cast<const uint64_t*>(ws + P.o_ttu);
+  a.n_vary = int32_t(P.vary.size());
+  a.n_uni = int32_t(P.uni.size());
+  for (int k = 0; k < a.n_vary; ++k) a.vary_sub[k] = P.vary[k];
+  for (int k = 0; k < a.n_uni; ++k) a.uni_sub[k] = P.uni[k];
+  a.n_c = P.n_c;
+  a.n_u = P.n_u;
   he = launch_cut(a, out_dev, stream);
   if (he != hipSuccess) return set_error(QSV_ERR_DEVICE, hipGetErrorString(he));
   return set_error(QSV_OK, "");

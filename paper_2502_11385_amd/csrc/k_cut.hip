@@ -78,25 +78,94 @@ __global__ void __launch_bounds__(256)
   a.T[sd.t_offset + local] = acc;
 }
 
+// The subcircuit's output index of outcome x (bit i = its i-th output).
+__device__ __forceinline__ uint64_t cut_gather(const CutSubDev& sd,
+                                               uint64_t x) {
+  uint64_t v = 0;
+  for (int r = 0; r < sd.n_runs; ++r)
+    v |= ((x >> sd.run_src[r]) & ((uint64_t(1) << sd.run_len[r]) - 1))
+         << sd.run_dst[r];
+  return v;
+}
+
+// One thread per outcome x: the sum over all 4^K term choices of the
+// product of the subcircuits' entries.
 __global__ void __launch_bounds__(256)
-    cut_kron_kernel(CutArgs a, double* __restrict__ out) {
+    cut_kron_simple_kernel(CutArgs a, const double* __restrict__ T,
+                           double* __restrict__ out) {
   const uint64_t x = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (x >= (uint64_t(1) << a.n_qubits)) return;
   uint64_t y[kCutMaxSub];
-  for (int s = 0; s < a.n_sub; ++s) {
-    const CutSubDev& sd = a.subs[s];
-    uint64_t v = 0;
-    for (int i = 0; i < sd.eff; ++i) v |= ((x >> sd.out_uncut[i]) & 1) << i;
-    y[s] = v;
-  }
+  for (int s = 0; s < a.n_sub; ++s) y[s] = cut_gather(a.subs[s], x);
   double acc = 0.0;
   for (uint64_t t = 0; t < a.n_terms; ++t) {
     const uint64_t* row = a.tt + t * uint64_t(a.n_sub);
     double prod = 1.0;
-    for (int s = 0; s < a.n_sub; ++s) prod *= a.T[row[s] + y[s]];
+    for (int s = 0; s < a.n_sub; ++s) prod *= T[row[s] + y[s]];
     acc += prod;
   }
   out[x] = acc * ldexp(1.0, -a.n_cuts);
+}
+
+
+// One wave per nb blocks of 64 consecutive outcomes (n_qubits >= 6).
+// Within a block the uniform subcircuits' entries are the same for every
+// lane, so the sum factors: p(x) = (1/2)^K sum_c W[c] prod_{varying s}
+// T_s(c)[y_s(x)], with W[c] = sum_u prod_{uniform s} T_s(c, u)[y_s].  The
+// wave first forms every block's products over the uniform subcircuits for
+// all (c, u) in parallel, then W[c] by summing over u in increasing order,
+// then each lane sums over c in increasing order for its outcomes.
+constexpr int kCutWaveLds = 512;  // doubles of LDS per wave
+
+__global__ void __launch_bounds__(256)
+    cut_kron_wave_kernel(CutArgs a, const double* __restrict__ T,
+                         double* __restrict__ out, int nb) {
+  __shared__ double lds[4][kCutWaveLds];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t nx = uint64_t(1) << a.n_qubits;
+  const uint64_t x0 = (uint64_t(blockIdx.x) * 4 + wv) * 64 * uint64_t(nb);
+  if (x0 >= nx) return;  // whole waves exit
+  double* P = lds[wv];                               // [nb][n_c][n_u]
+  double* W = P + uint64_t(nb) * a.n_c * a.n_u;      // [nb][n_c]
+  const uint64_t ncu = a.n_c * a.n_u;
+  for (uint64_t i = lane; i < uint64_t(nb) * ncu; i += 64) {
+    const uint64_t blk = i / ncu, cu = i - blk * ncu;
+    const uint64_t xb = x0 + blk * 64;
+    const uint64_t* row = a.ttu + cu * uint64_t(a.n_uni);
+    double prod = 1.0;
+    for (int k = 0; k < a.n_uni; ++k)
+      prod *= T[row[k] + cut_gather(a.subs[a.uni_sub[k]], xb)];
+    P[i] = prod;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (uint64_t i = lane; i < uint64_t(nb) * a.n_c; i += 64) {
+    double sum = 0.0;
+    for (uint64_t u = 0; u < a.n_u; ++u) sum += P[i * a.n_u + u];
+    W[i] = sum;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const double scale = ldexp(1.0, -a.n_cuts);
+  for (int blk = 0; blk < nb; ++blk) {
+    const uint64_t x = x0 + uint64_t(blk) * 64 + uint64_t(lane);
+    uint64_t yv[kCutMaxVary];
+#pragma unroll
+    for (int k = 0; k < kCutMaxVary; ++k)
+      yv[k] = k < a.n_vary ? cut_gather(a.subs[a.vary_sub[k]], x) : 0;
+    double acc = 0.0;
+    for (uint64_t c = 0; c < a.n_c; ++c) {
+      const uint64_t* row = a.ttv + c * uint64_t(a.n_vary);
+      double prod = W[uint64_t(blk) * a.n_c + c];
+#pragma unroll
+      for (int k = 0; k < kCutMaxVary; ++k)
+        if (k < a.n_vary) prod *= T[row[k] + yv[k]];
+      acc += prod;
+    }
+    out[x] = acc * scale;
+  }
 }
 
 hipError_t launch_cut(const CutArgs& a, double* out, hipStream_t stream) {
@@ -105,7 +174,20 @@ hipError_t launch_cut(const CutArgs& a, double* out, hipStream_t stream) {
     cut_terms_kernel<<<unsigned(blocks), 256, 0, stream>>>(a);
   }
   const uint64_t nx = uint64_t(1) << a.n_qubits;
-  cut_kron_kernel<<<unsigned((nx + 255) / 256), 256, 0, stream>>>(a, out);
+  // blocks of 64 outcomes per wave: up to 16, within the wave's LDS share
+  // (nb * n_c * (n_u + 1) doubles) and the number of blocks
+  int nb = 16;
+  while (nb > 1 && (uint64_t(nb) * a.n_c * (a.n_u + 1) > uint64_t(kCutWaveLds) ||
+                    uint64_t(nb) * 64 > nx))
+    nb >>= 1;
+  if (a.n_qubits >= 6 && a.n_vary <= kCutMaxVary &&
+      a.n_c * (a.n_u + 1) <= uint64_t(kCutWaveLds)) {
+    const uint64_t waves = nx / (64 * uint64_t(nb));
+    cut_kron_wave_kernel<<<unsigned((waves + 3) / 4), 256, 0, stream>>>(
+        a, a.T, out, nb);
+  } else
+    cut_kron_simple_kernel<<<unsigned((nx + 255) / 256), 256, 0, stream>>>(
+        a, a.T, out);
   return hipGetLastError();
 }
 
