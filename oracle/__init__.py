@@ -21,6 +21,9 @@ from .statevector import (  # noqa: F401
     splitmix64,
     uniforms,
     sample,
+    top_k,
+    probs_of_amplitudes,
+    pauli_expectation,
     cut_prologue,
     cut_epilogue,
     variant_probabilities,

@@ -256,6 +256,34 @@ def sample(p: np.ndarray, shots: int, seed: int) -> np.ndarray:
     return np.searchsorted(c, t, side="right").astype(np.uint64)
 
 
+def top_k(p: np.ndarray, k: int):
+    """The k largest entries of p: (indices, values), by value descending and
+    by index ascending among equal values."""
+    p = np.asarray(p, dtype=np.float64)
+    order = np.lexsort((np.arange(p.size), -p))[:k]
+    return order.astype(np.uint64), p[order]
+
+
+def probs_of_amplitudes(psi: np.ndarray) -> np.ndarray:
+    """|a|^2 as re*re + im*im, each product and the sum rounded separately
+    in FP64 (the key on which a top-k selection decides)."""
+    re = np.real(psi).astype(np.float64)
+    im = np.imag(psi).astype(np.float64)
+    return re * re + im * im
+
+
+def pauli_expectation(psi: np.ndarray, n: int, paulis) -> float:
+    """<psi| P |psi> for P = product over {qubit: 'X' | 'Y' | 'Z'}, by
+    applying P's one-qubit matrices to a copy of psi."""
+    mats = {"X": np.array([[0, 1], [1, 0]], dtype=complex),
+            "Y": np.array([[0, -1j], [1j, 0]], dtype=complex),
+            "Z": np.array([[1, 0], [0, -1]], dtype=complex)}
+    phi = np.asarray(psi, dtype=complex).copy()
+    for q, lab in paulis.items():
+        phi = apply_gate(phi, n, mats[lab], (q,))
+    return float(np.vdot(psi, phi).real)
+
+
 # ---------------------------------------------------------------------------
 # Cut variants (Section III.A, eqs 3.2-3.6)
 

@@ -383,6 +383,58 @@ def test_cut_reconstruction_detects_wrong_variant():
 
 
 # --------------------------------------------------------------------------
+# outputs: top-k probabilities and Pauli expectation values
+
+
+def test_top_k_against_python_sort_with_ties():
+    rng = np.random.default_rng(3)
+    p = rng.integers(0, 7, 200) / 8.0          # many equal values
+    for k in (1, 5, 37, 200):
+        idx, val = oracle.top_k(p, k)
+        want = sorted(range(200), key=lambda i: (-p[i], i))[:k]
+        assert idx.tolist() == want
+        assert val.tolist() == [p[i] for i in want]
+
+
+def test_probs_of_amplitudes_rounding():
+    a = np.array([0.1 + 0.7j, 1e-9 - 3e-9j], dtype=np.complex128)
+    want = [(0.1 * 0.1) + (0.7 * 0.7), (1e-9 * 1e-9) + (3e-9 * 3e-9)]
+    assert oracle.probs_of_amplitudes(a).tolist() == want
+    a32 = a.astype(np.complex64)
+    re, im = float(a32[0].real), float(a32[0].imag)
+    assert oracle.probs_of_amplitudes(a32)[0] == re * re + im * im
+
+
+def test_pauli_expectations_closed_forms():
+    n = 4
+    ghz = oracle.simulate(n, ghz_circuit(n))
+    assert abs(oracle.pauli_expectation(ghz, n, {0: "Z", 3: "Z"}) - 1) < 1e-14
+    assert abs(oracle.pauli_expectation(ghz, n, {0: "Z"})) < 1e-14
+    assert abs(oracle.pauli_expectation(
+        ghz, n, {q: "X" for q in range(n)}) - 1) < 1e-14
+    # GHZ: <Y Y X X> = -1 (two Y factors give i^2 on the |1111> -> |0000> term)
+    assert abs(oracle.pauli_expectation(
+        ghz, n, {0: "Y", 1: "Y", 2: "X", 3: "X"}) + 1) < 1e-14
+    # one qubit: the Bloch vector of a0|0> + a1|1>
+    rng = np.random.default_rng(4)
+    v = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+    v /= np.linalg.norm(v)
+    bloch = (2 * (np.conj(v[0]) * v[1]).real, 2 * (np.conj(v[0]) * v[1]).imag,
+             abs(v[0]) ** 2 - abs(v[1]) ** 2)
+    for lab, want in zip("XYZ", bloch):
+        assert abs(oracle.pauli_expectation(v, 1, {0: lab}) - want) < 1e-14
+
+
+def test_pauli_z_matches_marginal():
+    n = 6
+    psi = random_state(n, 8)
+    for q in range(n):
+        m = oracle.marginal(oracle.probabilities(psi), n, [q])
+        assert abs(oracle.pauli_expectation(psi, n, {q: "Z"}) -
+                   (m[0] - m[1])) < 1e-14
+
+
+# --------------------------------------------------------------------------
 # Table III
 
 
