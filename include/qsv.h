@@ -237,6 +237,27 @@ qsv_status qsv_marginal(qsv_state s, const int32_t* qubits, int32_t m,
 qsv_status qsv_sample(qsv_state s, uint64_t n_shots, uint64_t seed,
                       uint64_t* out_host);
 
+/* The k most probable outcomes (1 <= k <= min(65536, 2^n)): idx_out[k]
+ * and p_out[k] (host), ordered by probability, largest first, and by index
+ * among equal probabilities.  The probability of outcome i is decided as
+ * p = re*re + im*im in FP64 with each product and the sum rounded
+ * separately (for c64 the amplitudes are widened to FP64 first), so the
+ * selection equals that of any plain FP64 evaluation.  This is the literal
+ * top-k alternative to the marginal over specified qubits (Section IV.A).
+ * Reads the state about seven times (radix select on 12-bit digits), waits. */
+qsv_status qsv_top_k(qsv_state s, uint32_t k, uint64_t* idx_out,
+                     double* p_out);
+
+/* Expectation values <psi|P_t|psi> of n_terms Pauli strings (host arrays):
+ * x_masks[t] has bit q set where P_t acts on qubit q with X or Y, z_masks[t]
+ * where it acts with Z or Y (Y = i X Z).  out[t] (host) is the real value
+ * for the state as it is (not renormalised); sums are FP64 with Neumaier
+ * compensation in a fixed order.  Masks naming a qubit >= n are rejected.
+ * One read of the state (plus its partner amplitudes) per term; waits. */
+qsv_status qsv_expectation_pauli(qsv_state s, int32_t n_terms,
+                                 const uint64_t* x_masks,
+                                 const uint64_t* z_masks, double* out);
+
 /* ------------------------------------------------- batched cut variants */
 
 /* One subcircuit variant (Section III.A): a width-qubit circuit started in

@@ -816,6 +816,164 @@ qsv_status qsv_renormalize(qsv_state s, double* norm_out) {
   return QSV_OK;
 }
 
+// ------------------------------------------------------------- top-k
+
+qsv_status qsv_top_k(qsv_state s, uint32_t k, uint64_t* idx_out,
+                     double* p_out) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if (!idx_out || !p_out) return fail(QSV_ERR_INVALID_ARG, "null argument");
+  const uint64_t count = uint64_t(1) << s->n;
+  if (k < 1 || k > 65536 || uint64_t(k) > count)
+    return fail(QSV_ERR_INVALID_ARG, "k must be 1..min(65536, 2^n)");
+  if ((st = select_device(s)) != QSV_OK) return st;
+  // scratch: histogram, counter, k keys, k indices, tie counts/offsets
+  const unsigned tie_blocks = 1024;
+  const uint64_t chunk = (count + tie_blocks - 1) / tie_blocks;
+  const size_t o_cnt = 4096 * 8, o_key = o_cnt + 256, o_idx = o_key + 8 * size_t(k);
+  const size_t o_tc = (o_idx + 8 * size_t(k) + 255) & ~size_t(255);
+  const size_t o_to = o_tc + 8 * tie_blocks;
+  if ((st = ensure_scratch(s, o_to + 8 * tie_blocks)) != QSV_OK) return st;
+  char* sc = s->scratch;
+  auto* hist = reinterpret_cast<unsigned long long*>(sc);
+  auto* counter = reinterpret_cast<unsigned long long*>(sc + o_cnt);
+  auto* dkey = reinterpret_cast<uint64_t*>(sc + o_key);
+  auto* didx = reinterpret_cast<uint64_t*>(sc + o_idx);
+  auto* tcount = reinterpret_cast<unsigned long long*>(sc + o_tc);
+  auto* toff = reinterpret_cast<unsigned long long*>(sc + o_to);
+  // radix select of the k-th largest key, 12 bits per pass from the top
+  uint64_t prefix = 0, mask = 0, need = k, above = 0;
+  int fixed = 0;
+  bool whole_bin = false;
+  std::vector<unsigned long long> h(4096);
+  while (fixed < 64) {
+    const int wd = std::min(12, 64 - fixed);
+    const int shift = 64 - fixed - wd;
+    const int bins = 1 << wd;
+    QSV_HIP(s, hipMemsetAsync(hist, 0, 8 * size_t(bins), s->stream));
+    QSV_HIP(s, launch_topk_hist(s->prec, s->amp, count, mask, prefix, shift,
+                                bins, hist, s->stream));
+    QSV_HIP(s, hipMemcpyAsync(h.data(), hist, 8 * size_t(bins),
+                              hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(s, hipStreamSynchronize(s->stream));
+    uint64_t cum = 0;
+    int b = bins - 1;
+    for (; b > 0; --b) {
+      if (cum + h[b] >= need) break;
+      cum += h[b];
+    }
+    above += cum;
+    need -= cum;
+    prefix |= uint64_t(b) << shift;
+    mask |= uint64_t(bins - 1) << shift;
+    fixed += wd;
+    if (h[b] == need) {  // the whole bin is taken: keys >= its lower bound
+      whole_bin = true;
+      break;
+    }
+  }
+  std::vector<uint64_t> keys, idx;
+  if (whole_bin) {
+    QSV_HIP(s, hipMemsetAsync(counter, 0, 8, s->stream));
+    QSV_HIP(s, launch_topk_collect(s->prec, s->amp, count, mask, prefix, 1,
+                                   counter, k, dkey, didx, s->stream));
+    keys.resize(k);
+    idx.resize(k);
+    QSV_HIP(s, hipMemcpyAsync(keys.data(), dkey, 8 * size_t(k),
+                              hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(s, hipMemcpyAsync(idx.data(), didx, 8 * size_t(k),
+                              hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(s, hipStreamSynchronize(s->stream));
+  } else {
+    // prefix is the exact k-th key: `above` keys exceed it, `need` of the
+    // keys equal to it complete the k, in index order
+    keys.resize(k);
+    idx.resize(k);
+    if (above) {
+      QSV_HIP(s, hipMemsetAsync(counter, 0, 8, s->stream));
+      QSV_HIP(s, launch_topk_collect(s->prec, s->amp, count, ~uint64_t(0),
+                                     prefix, 0, counter, above, dkey, didx,
+                                     s->stream));
+      QSV_HIP(s, hipMemcpyAsync(keys.data(), dkey, 8 * above,
+                                hipMemcpyDeviceToHost, s->stream));
+      QSV_HIP(s, hipMemcpyAsync(idx.data(), didx, 8 * above,
+                                hipMemcpyDeviceToHost, s->stream));
+    }
+    QSV_HIP(s, launch_topk_ties(s->prec, s->amp, count, prefix, tie_blocks,
+                                chunk, tcount, nullptr, 0, nullptr,
+                                s->stream));
+    std::vector<unsigned long long> tc(tie_blocks), to(tie_blocks);
+    QSV_HIP(s, hipMemcpyAsync(tc.data(), tcount, 8 * tie_blocks,
+                              hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(s, hipStreamSynchronize(s->stream));
+    unsigned long long run = 0;
+    for (unsigned b = 0; b < tie_blocks; ++b) {
+      to[b] = run;
+      run += tc[b];
+    }
+    QSV_HIP(s, hipMemcpyAsync(toff, to.data(), 8 * tie_blocks,
+                              hipMemcpyHostToDevice, s->stream));
+    QSV_HIP(s, launch_topk_ties(s->prec, s->amp, count, prefix, tie_blocks,
+                                chunk, tcount, toff, need, didx + above,
+                                s->stream));
+    QSV_HIP(s, hipMemcpyAsync(idx.data() + above, didx + above, 8 * need,
+                              hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(s, hipStreamSynchronize(s->stream));
+    for (uint64_t i = above; i < k; ++i) keys[i] = prefix;
+  }
+  std::vector<uint32_t> ord(k);
+  for (uint32_t i = 0; i < k; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) {
+    if (keys[x] != keys[y]) return keys[x] > keys[y];
+    return idx[x] < idx[y];
+  });
+  for (uint32_t i = 0; i < k; ++i) {
+    idx_out[i] = idx[ord[i]];
+    const uint64_t kb = keys[ord[i]];
+    std::memcpy(&p_out[i], &kb, 8);
+  }
+  return QSV_OK;
+}
+
+// ------------------------------------------------- Pauli expectations
+
+qsv_status qsv_expectation_pauli(qsv_state s, int32_t n_terms,
+                                 const uint64_t* x_masks,
+                                 const uint64_t* z_masks, double* out) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if (n_terms < 1 || !x_masks || !z_masks || !out)
+    return fail(QSV_ERR_INVALID_ARG, "need n_terms >= 1 and non-null arrays");
+  const uint64_t full = (s->n >= 64) ? ~uint64_t(0)
+                                     : ((uint64_t(1) << s->n) - 1);
+  for (int t = 0; t < n_terms; ++t)
+    if ((x_masks[t] | z_masks[t]) & ~full)
+      return fail(QSV_ERR_INVALID_ARG, "Pauli mask names a qubit >= n");
+  if ((st = select_device(s)) != QSV_OK) return st;
+  const size_t part = (pauli_scratch_bytes(s->n) + 255) & ~size_t(255);
+  const size_t outb = 16 * size_t(n_terms);
+  if ((st = ensure_scratch(s, part + outb)) != QSV_OK) return st;
+  double* od = reinterpret_cast<double*>(s->scratch + part);
+  for (int t = 0; t < n_terms; ++t)
+    QSV_HIP(s, launch_pauli(s->prec, s->amp, s->n, x_masks[t], z_masks[t],
+                            reinterpret_cast<double*>(s->scratch), od + 2 * t,
+                            s->stream));
+  std::vector<double> sri(2 * size_t(n_terms));
+  QSV_HIP(s, hipMemcpyAsync(sri.data(), od, outb, hipMemcpyDeviceToHost,
+                            s->stream));
+  QSV_HIP(s, hipStreamSynchronize(s->stream));
+  for (int t = 0; t < n_terms; ++t) {
+    const double re = sri[2 * t], im = sri[2 * t + 1];
+    switch (__builtin_popcountll(x_masks[t] & z_masks[t]) & 3) {
+      case 0: out[t] = re; break;
+      case 1: out[t] = -im; break;
+      case 2: out[t] = -re; break;
+      default: out[t] = im; break;
+    }
+  }
+  return QSV_OK;
+}
+
 qsv_status qsv_marginal(qsv_state s, const int32_t* qubits, int32_t m,
                         double* out_host) {
   qsv_status st = check_state(s);

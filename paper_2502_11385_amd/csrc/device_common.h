@@ -104,6 +104,25 @@ hipError_t launch_marginal(int prec, const void* amp, int n,
                            const int32_t* qubits, int m, double* scratch,
                            double* out_dev, hipStream_t stream);
 size_t sample_scratch_bytes(int n, uint64_t shots);
+// top-k and Pauli expectations (k_outputs.hip)
+hipError_t launch_topk_hist(int prec, const void* amp, uint64_t count,
+                            uint64_t mask, uint64_t prefix, int shift,
+                            int bins, unsigned long long* hist,
+                            hipStream_t stream);
+hipError_t launch_topk_collect(int prec, const void* amp, uint64_t count,
+                               uint64_t mask, uint64_t prefix, int ge,
+                               unsigned long long* counter, uint64_t cap,
+                               uint64_t* out_key, uint64_t* out_idx,
+                               hipStream_t stream);
+hipError_t launch_topk_ties(int prec, const void* amp, uint64_t count,
+                            uint64_t key, unsigned blocks, uint64_t chunk,
+                            unsigned long long* counts,
+                            const unsigned long long* offsets, uint64_t need,
+                            uint64_t* out_idx, hipStream_t stream);
+size_t pauli_scratch_bytes(int n);
+hipError_t launch_pauli(int prec, const void* amp, int n, uint64_t xm,
+                        uint64_t zm, double* scratch, double* out_dev,
+                        hipStream_t stream);
 hipError_t launch_sample(int prec, const void* amp, int n, uint64_t shots,
                          uint64_t seed, void* scratch, uint64_t* out_dev,
                          hipStream_t stream);

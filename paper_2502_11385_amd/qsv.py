@@ -52,6 +52,7 @@ EXPORTED = [
     "qsv_server_release", "qsv_server_stats", "qsv_server_destroy",
     "qsv_clock", "qsv_debug_emulate_tiled",
     "qsv_cut_workspace_bytes", "qsv_cut_reconstruct",
+    "qsv_top_k", "qsv_expectation_pauli",
 ]
 
 
@@ -166,6 +167,8 @@ _SIGS = {
     "qsv_server_stats": [_p, _pu64, _i32],
     "qsv_server_destroy": [_p],
     "qsv_pass_times": [_p, C.POINTER(C.c_float), _pi32, _i32, _pi32],
+    "qsv_top_k": [_p, C.c_uint32, _pu64, _pd],
+    "qsv_expectation_pauli": [_p, _i32, _pu64, _pu64, _pd],
     "qsv_cut_workspace_bytes": [C.POINTER(qsv_cut_spec), _pu64],
     "qsv_cut_reconstruct": [C.POINTER(qsv_cut_spec), _p, _i32, _u64, _pu64,
                             _p, _u64, _p, _p],
@@ -463,6 +466,31 @@ class State:
         _check(_lib.qsv_sample(self._h, int(shots), int(seed),
                                _ptr(out, C.c_uint64)))
         return out[:shots]
+
+    def top_k(self, k: int):
+        """(indices, probabilities) of the k most probable outcomes."""
+        idx = np.zeros(max(int(k), 1), np.uint64)
+        p = np.zeros(max(int(k), 1), np.float64)
+        _check(_lib.qsv_top_k(self._h, int(k), _ptr(idx, C.c_uint64),
+                              _ptr(p, C.c_double)))
+        return idx[:k], p[:k]
+
+    def expectation(self, terms) -> np.ndarray:
+        """<P> for each term, a dict {qubit: 'X' | 'Y' | 'Z'}."""
+        xm = np.zeros(len(terms), np.uint64)
+        zm = np.zeros(len(terms), np.uint64)
+        for t, term in enumerate(terms):
+            for q, lab in term.items():
+                if lab in ("X", "Y"):
+                    xm[t] |= np.uint64(1 << q)
+                if lab in ("Z", "Y"):
+                    zm[t] |= np.uint64(1 << q)
+        out = np.zeros(len(terms), np.float64)
+        _check(_lib.qsv_expectation_pauli(self._h, len(terms),
+                                          _ptr(xm, C.c_uint64),
+                                          _ptr(zm, C.c_uint64),
+                                          _ptr(out, C.c_double)))
+        return out
 
     def get(self) -> np.ndarray:
         out = np.zeros(1 << self.n, self.amp_dtype)
