@@ -460,6 +460,20 @@ def main() -> int:
                      "avg_launch_ms": round(avg_ms, 4),
                      "launches": int(sel.size)},
     }
+    # further outputs of the final state (outside the timed step)
+    t0 = time.perf_counter()
+    tk_idx, tk_p = state.top_k(1024)
+    t1 = time.perf_counter()
+    terms = [{0: "Z", 1: "Z"}, {n - 1: "X", n - 2: "X"}, {5: "Y", 17: "Y"},
+             {q: "Z" for q in range(n)}]
+    ev = state.expectation(terms)
+    t2 = time.perf_counter()
+    out["outputs"] = {"top_k": 1024, "top_k_ms": round((t1 - t0) * 1e3, 3),
+                      "top1_p": float(tk_p[0]),
+                      "pauli_terms": len(terms),
+                      "pauli_ms_per_term": round((t2 - t1) * 1e3 / len(terms),
+                                                 3),
+                      "pauli_values": [float(v) for v in ev]}
     state.free()
     del probs
     torch.cuda.empty_cache()
