@@ -468,6 +468,23 @@ def main() -> int:
              {q: "Z" for q in range(n)}]
     ev = state.expectation(terms)
     t2 = time.perf_counter()
+    # relabelling pass (reverse qubit order and back), HIP-event timed
+    rev = list(reversed(range(n)))
+    state.permute_qubits(rev)                    # allocates its buffer
+    state.permute_qubits(rev)
+    torch.cuda.synchronize()
+    pe0 = torch.cuda.Event(enable_timing=True)
+    pe1 = torch.cuda.Event(enable_timing=True)
+    pe0.record()
+    state.permute_qubits(rev)
+    state.permute_qubits(rev)
+    pe1.record()
+    torch.cuda.synchronize()
+    perm_ms = pe0.elapsed_time(pe1) / 2
+    out["permute"] = {"workload": f"reverse the order of {n} qubits",
+                      "ms": round(perm_ms, 3),
+                      "GBps": round(2 * state_bytes / (perm_ms * 1e-3) / 1e9,
+                                    1)}
     out["outputs"] = {"top_k": 1024, "top_k_ms": round((t1 - t0) * 1e3, 3),
                       "top1_p": float(tk_p[0]),
                       "pauli_terms": len(terms),

@@ -237,6 +237,17 @@ qsv_status qsv_marginal(qsv_state s, const int32_t* qubits, int32_t m,
 qsv_status qsv_sample(qsv_state s, uint64_t n_shots, uint64_t seed,
                       uint64_t* out_host);
 
+/* Relabel qubits: qubit q becomes qubit perm[q] (perm: host, a
+ * permutation of 0..n-1), i.e. the amplitude of index i moves to the index
+ * whose bit perm[q] is bit q of i.  This is the data movement of the
+ * paper's swap insertion (Section III.B): one pass that brings busy high
+ * qubits to low positions.  Out of place into a second state-sized buffer
+ * that the state allocates on first use and keeps until qsv_free; for a
+ * state from qsv_alloc the two buffers then trade places (the device
+ * pointer reported by qsv_info changes), for a wrapped state the result is
+ * copied back.  Pure data movement: bit-exact.  Asynchronous. */
+qsv_status qsv_permute_qubits(qsv_state s, const int32_t* perm);
+
 /* The k most probable outcomes (1 <= k <= min(65536, 2^n)): idx_out[k]
  * and p_out[k] (host), ordered by probability, largest first, and by index
  * among equal probabilities.  The probability of outcome i is decided as

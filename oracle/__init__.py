@@ -22,6 +22,7 @@ from .statevector import (  # noqa: F401
     uniforms,
     sample,
     top_k,
+    permute_qubits,
     probs_of_amplitudes,
     pauli_expectation,
     cut_prologue,

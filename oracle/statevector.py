@@ -256,6 +256,17 @@ def sample(p: np.ndarray, shots: int, seed: int) -> np.ndarray:
     return np.searchsorted(c, t, side="right").astype(np.uint64)
 
 
+def permute_qubits(psi: np.ndarray, n: int, perm) -> np.ndarray:
+    """Relabel qubits: qubit q becomes qubit perm[q], i.e. the amplitude of
+    index i moves to the index whose bit perm[q] is bit q of i."""
+    t = np.asarray(psi).reshape((2,) * n)
+    # axis n-1-q holds qubit q; new axis n-1-perm[q] must hold old qubit q
+    src_axis_for_new = [0] * n
+    for q in range(n):
+        src_axis_for_new[n - 1 - perm[q]] = n - 1 - q
+    return np.transpose(t, src_axis_for_new).reshape(-1).copy()
+
+
 def top_k(p: np.ndarray, k: int):
     """The k largest entries of p: (indices, values), by value descending and
     by index ascending among equal values."""

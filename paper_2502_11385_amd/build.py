@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build", "qsv")
 LIB = os.path.join(HERE, "libqsv.so")
 
 SOURCES = ["api.cpp", "planner.cpp", "batch.cpp", "server.cpp", "cut.cpp",
-           "k_outputs.hip",
+           "k_outputs.hip", "k_permute.hip",
            "k_gate.hip", "k_cut.hip",
            "k_tile.hip", "k_reduce.hip", "k_fused.hip", "k_batch.hip"]
 

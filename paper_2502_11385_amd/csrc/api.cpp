@@ -34,6 +34,8 @@ struct qsv_state_s {
   size_t host_cap = 0;
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
+  // second state-sized buffer for out-of-place relabelling (on demand)
+  void* spare = nullptr;
   // reduction scratch
   char* scratch = nullptr;
   size_t scratch_cap = 0;
@@ -278,6 +280,7 @@ qsv_status qsv_free(qsv_state s) {
   if (s->owned && s->amp) (void)hipFree(s->amp);
   if (s->prog_dev) (void)hipFree(s->prog_dev);
   if (s->scratch) (void)hipFree(s->scratch);
+  if (s->spare) (void)hipFree(s->spare);
   if (s->prog_host) (void)hipHostFree(s->prog_host);
   if (s->upload_done) (void)hipEventDestroy(s->upload_done);
   for (hipEvent_t e2 : s->evs) (void)hipEventDestroy(e2);
@@ -813,6 +816,63 @@ qsv_status qsv_renormalize(qsv_state s, double* norm_out) {
   QSV_HIP(s, launch_scale(s->prec, s->amp, s->n, nd, s->stream));
   QSV_HIP(s, hipStreamSynchronize(s->stream));
   if (norm_out) *norm_out = h;
+  return QSV_OK;
+}
+
+// -------------------------------------------------- qubit relabelling
+
+qsv_status qsv_permute_qubits(qsv_state s, const int32_t* perm) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if (!perm) return fail(QSV_ERR_INVALID_ARG, "null permutation");
+  const int n = s->n;
+  std::vector<int> inv(n, -1);
+  for (int q = 0; q < n; ++q) {
+    if (perm[q] < 0 || perm[q] >= n || inv[perm[q]] >= 0)
+      return fail(QSV_ERR_INVALID_ARG, "perm must be a permutation of 0..n-1");
+    inv[perm[q]] = q;
+  }
+  bool identity = true;
+  for (int q = 0; q < n; ++q) identity = identity && perm[q] == q;
+  if (identity) return QSV_OK;
+  if ((st = select_device(s)) != QSV_OK) return st;
+  // tile source bits: the m lowest, and those that land on the m lowest
+  const int m = std::min(n, s->b == 8 ? 5 : 4);
+  uint64_t smask = 0;
+  for (int q = 0; q < m; ++q) smask |= (uint64_t(1) << q) | (uint64_t(1) << inv[q]);
+  PermArgs pa = {};
+  for (int q = 0; q < n; ++q)
+    if (smask >> q & 1) pa.s_bits[pa.s++] = q;
+    else {
+      pa.outer_src[pa.n_outer] = q;
+      pa.outer_dst[pa.n_outer++] = perm[q];
+    }
+  std::vector<int> d(pa.s_bits, pa.s_bits + pa.s);
+  for (int& x : d) x = perm[x];
+  std::sort(d.begin(), d.end());
+  for (int j = 0; j < pa.s; ++j) {
+    pa.d_bits[j] = d[j];
+    const int q = inv[d[j]];
+    for (int k = 0; k < pa.s; ++k)
+      if (pa.s_bits[k] == q) pa.src_of[j] = k;
+  }
+  const size_t bytes = size_t(s->b) << n;
+  if (!s->spare) {
+    QSV_HIP(s, hipStreamSynchronize(s->stream));
+    hipError_t e = hipMalloc(&s->spare, bytes);
+    if (e != hipSuccess) {
+      s->spare = nullptr;
+      (void)hipGetLastError();
+      return fail(QSV_ERR_OUT_OF_MEMORY, "no room for the relabelling buffer");
+    }
+  }
+  QSV_HIP(s, launch_permute(s->prec, s->amp, s->spare, n, pa, s->stream));
+  if (s->owned) {
+    std::swap(s->amp, s->spare);
+  } else {
+    QSV_HIP(s, hipMemcpyAsync(s->amp, s->spare, bytes, hipMemcpyDeviceToDevice,
+                              s->stream));
+  }
   return QSV_OK;
 }
 

@@ -119,6 +119,21 @@ hipError_t launch_topk_ties(int prec, const void* amp, uint64_t count,
                             unsigned long long* counts,
                             const unsigned long long* offsets, uint64_t need,
                             uint64_t* out_idx, hipStream_t stream);
+// qubit relabelling (k_permute.hip): tile source bits s_bits (ascending,
+// s of them), their destinations d_bits (ascending), destination tile bit j
+// taken from source tile bit src_of[j], and the outer source bits with their
+// destinations
+struct PermArgs {
+  int32_t s;
+  int32_t n_outer;
+  int32_t s_bits[10];
+  int32_t d_bits[10];
+  int32_t src_of[10];
+  int32_t outer_src[34];
+  int32_t outer_dst[34];
+};
+hipError_t launch_permute(int prec, const void* src, void* dst, int n,
+                          const PermArgs& p, hipStream_t stream);
 size_t pauli_scratch_bytes(int n);
 hipError_t launch_pauli(int prec, const void* amp, int n, uint64_t xm,
                         uint64_t zm, double* scratch, double* out_dev,

@@ -52,7 +52,7 @@ EXPORTED = [
     "qsv_server_release", "qsv_server_stats", "qsv_server_destroy",
     "qsv_clock", "qsv_debug_emulate_tiled",
     "qsv_cut_workspace_bytes", "qsv_cut_reconstruct",
-    "qsv_top_k", "qsv_expectation_pauli",
+    "qsv_top_k", "qsv_expectation_pauli", "qsv_permute_qubits",
 ]
 
 
@@ -168,6 +168,7 @@ _SIGS = {
     "qsv_server_destroy": [_p],
     "qsv_pass_times": [_p, C.POINTER(C.c_float), _pi32, _i32, _pi32],
     "qsv_top_k": [_p, C.c_uint32, _pu64, _pd],
+    "qsv_permute_qubits": [_p, _pi32],
     "qsv_expectation_pauli": [_p, _i32, _pu64, _pu64, _pd],
     "qsv_cut_workspace_bytes": [C.POINTER(qsv_cut_spec), _pu64],
     "qsv_cut_reconstruct": [C.POINTER(qsv_cut_spec), _p, _i32, _u64, _pu64,
@@ -466,6 +467,11 @@ class State:
         _check(_lib.qsv_sample(self._h, int(shots), int(seed),
                                _ptr(out, C.c_uint64)))
         return out[:shots]
+
+    def permute_qubits(self, perm) -> None:
+        """Qubit q becomes qubit perm[q]."""
+        p = np.ascontiguousarray(perm, dtype=np.int32)
+        _check(_lib.qsv_permute_qubits(self._h, _ptr(p, C.c_int32)))
 
     def top_k(self, k: int):
         """(indices, probabilities) of the k most probable outcomes."""

@@ -1,0 +1,98 @@
+"""Qubit relabelling on the GPU against the oracle (bit-exact: the pass only
+moves data), and at 30 qubits by gate relabelling and round trips."""
+import numpy as np
+import pytest
+
+import oracle
+from circuits import random_state
+
+torch = pytest.importorskip("torch")
+from paper_2502_11385_amd import qsv  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+C64, C128 = qsv.QSV_C64, qsv.QSV_C128
+DT = {C64: np.complex64, C128: np.complex128}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("prec", [C64, C128])
+@pytest.mark.parametrize("n,seed", [(1, 1), (3, 2), (6, 3), (10, 4), (16, 5),
+                                    (20, 6)])
+def test_permute_matches_oracle_exactly(prec, n, seed):
+    rng = np.random.default_rng(seed)
+    psi = random_state(n, seed).astype(DT[prec])
+    s = qsv.State(n, prec)
+    for trial in range(3):
+        perm = rng.permutation(n).tolist()
+        if trial == 2:
+            perm = list(reversed(range(n)))       # all high <-> low
+        s.set(psi)
+        s.permute_qubits(perm)
+        got = s.get()
+        want = oracle.permute_qubits(psi, n, perm)
+        assert np.array_equal(got, want), perm
+    s.free()
+
+
+def test_permute_wrapped_state_copies_back():
+    n = 12
+    psi = random_state(n, 9).astype(np.complex64)
+    t = torch.from_numpy(psi.copy()).cuda()
+    s = qsv.State(n, C64, tensor=t)
+    perm = np.random.default_rng(9).permutation(n).tolist()
+    s.permute_qubits(perm)
+    s.sync()
+    assert np.array_equal(t.cpu().numpy(), oracle.permute_qubits(psi, n, perm))
+    s.free()
+
+
+def test_invalid_permutation_rejected():
+    s = qsv.State(5, C64)
+    s.init_basis(0)
+    for bad in ([0, 1, 2, 3, 3], [0, 1, 2, 3, 5], [-1, 1, 2, 3, 4]):
+        with pytest.raises(qsv.QsvError) as e:
+            s.permute_qubits(bad)
+        assert e.value.status == qsv.QSV_ERR_INVALID_ARG
+    s.free()
+
+
+def test_30q_gate_relabelling_and_round_trip():
+    """At full size, in the launch configuration the library uses: a gate on
+    qubit q before relabelling equals the gate on perm[q] after it, and the
+    inverse relabelling restores the state bit for bit."""
+    n = 30
+    rng = np.random.default_rng(30)
+    perm = rng.permutation(n).tolist()
+    inv = [0] * n
+    for q in range(n):
+        inv[perm[q]] = q
+    u3 = qsv.gate_matrix("u3", (0.7, 0.2, -1.3))
+    h = qsv.gate_matrix("h")
+    ta = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+    tb = torch.empty_like(ta)
+    a = qsv.State(n, C64, tensor=ta)
+    b = qsv.State(n, C64, tensor=tb)
+    for s in (a, b):
+        s.init_basis(12345)
+        for q in range(0, n, 3):
+            s.apply_gate([q], h)
+    # a: U on 29, then relabel; b: relabel, then U on perm[29]
+    a.apply_gate([29], u3)
+    a.permute_qubits(perm)
+    b.permute_qubits(perm)
+    b.apply_gate([perm[29]], u3)
+    torch.cuda.synchronize()
+    assert float((ta - tb).abs().max()) < 1e-6
+    before = tb.clone()
+    b.permute_qubits(inv)
+    b.permute_qubits(perm)
+    torch.cuda.synchronize()
+    assert torch.equal(before, tb)
+    a.free()
+    b.free()

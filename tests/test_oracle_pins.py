@@ -383,6 +383,36 @@ def test_cut_reconstruction_detects_wrong_variant():
 
 
 # --------------------------------------------------------------------------
+# qubit permutation
+
+
+def test_permute_qubits_brute_force_and_gate_relabelling():
+    n = 6
+    rng = np.random.default_rng(11)
+    psi = random_state(n, 11)
+    for _ in range(5):
+        perm = rng.permutation(n).tolist()
+        got = oracle.permute_qubits(psi, n, perm)
+        want = np.zeros_like(psi)
+        for i in range(1 << n):
+            j = 0
+            for q in range(n):
+                j |= ((i >> q) & 1) << perm[q]
+            want[j] = psi[i]
+        assert np.array_equal(got, want)
+        # a gate on qubit q before relabelling acts on perm[q] after it
+        u = oracle.gate_spec("u3", (2,), (0.3, 1.1, -0.4))[2]
+        a = oracle.permute_qubits(oracle.apply_gate(psi, n, u, (2,)), n, perm)
+        b = oracle.apply_gate(oracle.permute_qubits(psi, n, perm), n, u,
+                              (perm[2],))
+        assert np.max(np.abs(a - b)) < 1e-15
+        inv = [0] * n
+        for q in range(n):
+            inv[perm[q]] = q
+        assert np.array_equal(oracle.permute_qubits(got, n, inv), psi)
+
+
+# --------------------------------------------------------------------------
 # outputs: top-k probabilities and Pauli expectation values
 
 
