@@ -841,6 +841,7 @@ qsv_status qsv_permute_qubits(qsv_state s, const int32_t* perm) {
   uint64_t smask = 0;
   for (int q = 0; q < m; ++q) smask |= (uint64_t(1) << q) | (uint64_t(1) << inv[q]);
   PermArgs pa = {};
+  pa.m = m;
   for (int q = 0; q < n; ++q)
     if (smask >> q & 1) pa.s_bits[pa.s++] = q;
     else {
@@ -855,6 +856,23 @@ qsv_status qsv_permute_qubits(qsv_state s, const int32_t* perm) {
     const int q = inv[d[j]];
     for (int k = 0; k < pa.s; ++k)
       if (pa.s_bits[k] == q) pa.src_of[j] = k;
+  }
+  // uniform per-step parts of the tile index maps (see the kernel)
+  const uint32_t step = std::min(256u, 1u << pa.s);
+  pa.ne = int32_t((1u << pa.s) / step);
+  for (int e = 0; e < pa.ne; ++e) {
+    const uint32_t r = uint32_t(e) * step;
+    uint64_t sv = 0, dv = 0;
+    uint32_t gv = 0;
+    for (int j = 0; j < pa.s; ++j) {
+      const uint32_t bit = (r >> j) & 1u;
+      sv |= uint64_t(bit) << pa.s_bits[j];
+      dv |= uint64_t(bit) << pa.d_bits[j];
+      gv |= bit << pa.src_of[j];
+    }
+    pa.se[e] = sv;
+    pa.de[e] = dv;
+    pa.ge[e] = gv;
   }
   const size_t bytes = size_t(s->b) << n;
   if (!s->spare) {

@@ -126,6 +126,13 @@ hipError_t launch_topk_ties(int prec, const void* amp, uint64_t count,
 struct PermArgs {
   int32_t s;
   int32_t n_outer;
+  int32_t m;  // lowest qubits kept contiguous (the LDS slot fold width)
+  int32_t ne; // steps of blockDim.x amplitudes per tile
+  // per step e (r = e * blockDim.x + tid): the uniform parts of the source
+  // spread, the destination spread and the destination-to-source map
+  uint64_t se[16];
+  uint64_t de[16];
+  uint32_t ge[16];
   int32_t s_bits[10];
   int32_t d_bits[10];
   int32_t src_of[10];

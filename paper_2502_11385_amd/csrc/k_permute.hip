@@ -21,6 +21,13 @@ __device__ __forceinline__ uint64_t spread_bits(uint32_t x, const int* pos,
   return v;
 }
 
+// LDS slot of tile-local index r: its bits m.. folded onto bits 0..m-1 so
+// that both the loads (r consecutive) and the stores (r varying in the
+// bits that land on the lowest destination qubits) spread over banks.
+__device__ __forceinline__ uint32_t perm_slot(uint32_t r, int m) {
+  return r ^ ((r >> m) & ((1u << m) - 1u));
+}
+
 template <typename C>
 __global__ void __launch_bounds__(256)
     permute_kernel(const C* __restrict__ src, C* __restrict__ dst,
@@ -28,29 +35,37 @@ __global__ void __launch_bounds__(256)
   extern __shared__ double lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
   const uint32_t tid = threadIdx.x;
-  const uint32_t tile_amps = 1u << p.s;
+  const uint32_t step = blockDim.x;
   // tile index -> source base (outer source bits) and its destination
-  uint64_t t = blockIdx.x;
+  const uint64_t t = blockIdx.x;
   uint64_t sb = 0, db = 0;
   for (int j = 0; j < p.n_outer; ++j) {
     const uint64_t bit = (t >> j) & 1;
     sb |= bit << p.outer_src[j];
     db |= bit << p.outer_dst[j];
   }
-  for (uint32_t r = tid; r < tile_amps; r += blockDim.x)
-    lds[r] = src[sb | spread_bits(r, p.s_bits, p.s)];
-  __syncthreads();
-  for (uint32_t rd = tid; rd < tile_amps; rd += blockDim.x) {
-    // destination tile-local bit j holds source tile-local bit src_of[j]
-    uint32_t r = 0;
-    for (int j = 0; j < p.s; ++j) r |= ((rd >> j) & 1u) << p.src_of[j];
-    dst[db | spread_bits(rd, p.d_bits, p.s)] = lds[r];
+  // Spreading and the destination-to-source bit map are linear, and the
+  // thread and step parts of r = tid + e * step have disjoint bits, so each
+  // splits into a per-thread term and a per-step (uniform) term.
+  const uint64_t s_thr = spread_bits(tid, p.s_bits, p.s);
+  const uint64_t d_thr = spread_bits(tid, p.d_bits, p.s);
+  uint32_t g_thr = 0;
+  for (int j = 0; j < p.s; ++j) g_thr |= ((tid >> j) & 1u) << p.src_of[j];
+  for (int e = 0; e < p.ne; ++e) {
+    const uint32_t r = uint32_t(e) * step + tid;
+    lds[perm_slot(r, p.m)] = src[sb | s_thr | p.se[e]];
   }
+  __syncthreads();
+  for (int e = 0; e < p.ne; ++e)
+    dst[db | d_thr | p.de[e]] = lds[perm_slot(g_thr | p.ge[e], p.m)];
 }
 
 hipError_t launch_permute(int prec, const void* src, void* dst, int n,
                           const PermArgs& p, hipStream_t stream) {
-  if (p.s < 0 || p.s > kPermMaxTileBits || p.s > n) return hipErrorInvalidValue;
+  if (p.s < 0 || p.s > kPermMaxTileBits || p.s > n || p.m < 0 || p.m > p.s ||
+      p.ne < 1 || p.ne > 16 ||
+      uint64_t(p.ne) * ((1u << p.s) < 256u ? (1u << p.s) : 256u) != (1ull << p.s))
+    return hipErrorInvalidValue;
   const uint64_t tiles = uint64_t(1) << (n - p.s);
   const unsigned threads = (1u << p.s) < 256u ? (1u << p.s) : 256u;
   if (prec == 1)
