@@ -296,7 +296,8 @@ typedef struct {
  *   tile_log2 : tile size for every variant wider than it (default 12 c64,
  *               11 c128); variants at most this wide run in one tile
  *   reg_log2  : amplitudes per thread, as log2 (4, or 5 for c64)
- *   grid      : work-groups of the persistent launch (default 3 per CU)
+ *   grid      : work-groups of the persistent launch (default: as many as
+ *               stay resident, from the kernel's occupancy)
  *   autotune  : time (tile_log2, reg_log2) candidates at creation and keep
  *               the fastest
  *   use_graph : capture the launch in a hipGraph and replay it

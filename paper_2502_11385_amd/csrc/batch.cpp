@@ -182,6 +182,8 @@ struct qsv_batch_s {
   int device = 0;
   size_t count = 0;
   int L = 12, RB = 4, grid = 0;
+  int user_grid = 0;  // 0: as many work-groups as stay resident
+  int cus = 0;
   bool use_graph = false;
   HostProgram hp;
   char* prog = nullptr;
@@ -215,6 +217,12 @@ qsv_status upload_program(qsv_batch b, const qsv_variant* vars, int L, int RB) {
   release_device(b);
   b->L = L;
   b->RB = RB;
+  if (b->user_grid) {
+    b->grid = b->user_grid;
+  } else {
+    const int per_cu = batch_blocks_per_cu(b->prec, b->out_fp64, RB, L);
+    b->grid = std::max(1, per_cu) * std::max(1, b->cus);
+  }
   std::vector<char> buf;
   b->o_circ = put(buf, b->hp.circs);
   b->o_order = put(buf, b->hp.order);
@@ -291,7 +299,8 @@ qsv_status qsv_batch_create(const qsv_variant* vars, size_t count,
   bt->stream = static_cast<hipStream_t>(stream);
   bt->device = dev;
   bt->count = count;
-  bt->grid = o.grid ? o.grid : 3 * cus;
+  bt->user_grid = o.grid;
+  bt->cus = cus;
   bt->use_graph = o.use_graph != 0;
   qsv_status st = upload_program(bt, vars, L, RB);
   if (st != QSV_OK) {

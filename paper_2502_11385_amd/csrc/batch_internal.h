@@ -39,6 +39,9 @@ inline bool batchable(const std::vector<HostGate>& G) {
   return true;
 }
 
+// Resident work-groups per CU of the batch kernel (0 if the query fails).
+int batch_blocks_per_cu(int prec, int out_fp64, int rb, int L);
+
 hipError_t launch_batch(int prec, int out_fp64, int rb, const BatchCircuit* circs,
                         const int32_t* order, int32_t count,
                         const TilePass* passes, const TileSeg* segs,

@@ -39,33 +39,46 @@ __global__ void __launch_bounds__(256)
       const bool active = tid < (1u << (L - RB));
       const bool first = pi == 0, last = pi + 1 == c.n_passes;
       const uint64_t ntiles = uint64_t(1) << (c.w - L);
+      // I/O layout: element index = tile base | register part | thread
+      // part; a variant has at most 2^24 amplitudes, so every offset inside
+      // the slot or the variant's output fits 32 bits
+      const uint32_t thr = active ? io_thread_index<RB>(pass, tid) : 0u;
+      uint64_t roff[R];
+      io_reg_offsets<C, RB>(pass, roff);  // bytes of C
       for (uint64_t t = 0; t < ntiles; ++t) {
         uint64_t base = t;
         for (int b = 0; b < L; ++b) base = insert_zero64(base, pass->q[b]);
-        uint64_t gthr, greg[RB];
-        io_offsets<RB>(pass, base, active ? tid : 0u, &gthr, greg);
+        const char* sb = reinterpret_cast<const char*>(slot + base);
         C a[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-          const uint64_t g = io_addr<RB>(gthr, greg, j);
           if (!first && active) {
-            a[j] = slot[g];
+            a[j] = load_at(slot, raw_rsrc<C>(sb + roff[j]),
+                           thr * uint32_t(sizeof(C)));
           } else {
-            a[j].x = (first && active && g == 0) ? T(1) : T(0);
+            const bool one = first && active && base == 0 && roff[j] == 0 &&
+                             thr == 0;
+            a[j].x = one ? T(1) : T(0);
             a[j].y = T(0);
           }
         }
         tile_apply<T, RB>(a, lds, pass, segs, ops, base, tid, active);
         if (active) {
+          if (last) {
+            const char* ob =
+                reinterpret_cast<const char*>(out + c.out_offset + base);
 #pragma unroll
-          for (int j = 0; j < R; ++j) {
-            const uint64_t g = io_addr<RB>(gthr, greg, j);
-            if (last) {
+            for (int j = 0; j < R; ++j) {
               const double x = double(a[j].x), y = double(a[j].y);
-              out[c.out_offset + g] = OUT(x * x + y * y);
-            } else {
-              slot[g] = a[j];
+              const uint64_t ro = roff[j] / sizeof(C) * sizeof(OUT);
+              store_at(raw_rsrc<OUT>(ob + ro), thr * uint32_t(sizeof(OUT)),
+                       OUT(x * x + y * y));
             }
+          } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+              store_at(raw_rsrc<C>(sb + roff[j]), thr * uint32_t(sizeof(C)),
+                       a[j]);
           }
         }
       }
@@ -97,6 +110,35 @@ static hipError_t batch_launch_t(const BatchCircuit* circs,
       circs, order, count, passes, segs, ops, static_cast<OUT*>(out),
       static_cast<C*>(scratch), slot_amps);
   return hipGetLastError();
+}
+
+// Resident work-groups per CU of the batch kernel for (prec, out, rb, L).
+template <typename T, typename OUT, int RB>
+static int batch_occupancy_t(int L) {
+  using C = typename CxT<T>::type;
+  (void)hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&batch_kernel<T, OUT, RB>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &n, reinterpret_cast<const void*>(&batch_kernel<T, OUT, RB>), 256,
+          size_t(sizeof(C)) << L) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
+int batch_blocks_per_cu(int prec, int out_fp64, int rb, int L) {
+  if (prec == 1) {
+    if (rb == 4)
+      return out_fp64 ? batch_occupancy_t<float, double, 4>(L)
+                      : batch_occupancy_t<float, float, 4>(L);
+    return out_fp64 ? batch_occupancy_t<float, double, 5>(L)
+                    : batch_occupancy_t<float, float, 5>(L);
+  }
+  return out_fp64 ? batch_occupancy_t<double, double, 4>(L)
+                  : batch_occupancy_t<double, float, 4>(L);
 }
 
 hipError_t launch_batch(int prec, int out_fp64, int rb, const BatchCircuit* circs,

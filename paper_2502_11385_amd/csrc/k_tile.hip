@@ -19,19 +19,6 @@
 
 namespace qsv {
 
-// Byte offset of register j of the I/O layout within a tile (uniform).
-template <typename C, int RB>
-__device__ __forceinline__ void io_reg_offsets(const TilePass* pass,
-                                               uint64_t* roff) {
-  const int W = pass->L - RB;
-  roff[0] = 0;
-#pragma unroll
-  for (int j = 1; j < (1 << RB); ++j) {
-    const int i = __builtin_ctz(j);
-    roff[j] = roff[j & (j - 1)] + (uint64_t(sizeof(C)) << pass->q[W + i]);
-  }
-}
-
 // Tile index -> global index of the tile's first amplitude: the index's
 // bits spread over the non-tile qubits.
 __device__ __forceinline__ uint64_t tile_base(const TilePass* pass,
@@ -40,14 +27,6 @@ __device__ __forceinline__ uint64_t tile_base(const TilePass* pass,
   const int L = pass->L;
   for (int b = 0; b < L; ++b) base = insert_zero64(base, pass->q[b]);
   return base;
-}
-
-template <typename C>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* p) {
-  // stride 0 (raw), the full 32-bit byte range, gfx9 word-3 layout with a
-  // 32-bit data format; offsets used here stay below 2^31
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), short(0),
-                                           int(0xffffffffu), 0x00020000);
 }
 
 // One tile per work-group.  At most 512 threads per tile (L - RB <= 9).

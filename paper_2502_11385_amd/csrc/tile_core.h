@@ -417,6 +417,39 @@ __device__ __forceinline__ uint32_t io_thread_boff(const TilePass* pass,
   return o * uint32_t(sizeof(C));
 }
 
+// Byte offset of register j of the I/O layout within a tile (uniform).
+template <typename C, int RB>
+__device__ __forceinline__ void io_reg_offsets(const TilePass* pass,
+                                               uint64_t* roff) {
+  const int W = pass->L - RB;
+  roff[0] = 0;
+#pragma unroll
+  for (int j = 1; j < (1 << RB); ++j) {
+    const int i = __builtin_ctz(j);
+    roff[j] = roff[j & (j - 1)] + (uint64_t(sizeof(C)) << pass->q[W + i]);
+  }
+}
+
+template <typename C>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* p) {
+  // stride 0 (raw), the full 32-bit byte range, gfx9 word-3 layout with a
+  // 32-bit data format; offsets used here stay below 2^31
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), short(0),
+                                           int(0xffffffffu), 0x00020000);
+}
+
+// Element index of a thread's part of the I/O layout (its tile-local
+// thread bits spread over the tile qubits).
+template <int RB>
+__device__ __forceinline__ uint32_t io_thread_index(const TilePass* pass,
+                                                    uint32_t tid) {
+  const int W = pass->L - RB;
+  uint32_t o = 0;
+  for (int b = 0; b < W; ++b)
+    if (tid >> b & 1) o |= 1u << pass->q[b];
+  return o;
+}
+
 // Raw buffer loads and stores at a 32-bit byte offset from a uniform buffer
 // resource (no per-access 64-bit vector address arithmetic).
 __device__ __forceinline__ float2 load_at(const float2*,
@@ -435,6 +468,17 @@ __device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r,
                                          uint32_t boff, float2 v) {
   using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, boff, 0, 0);
+}
+__device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r,
+                                         uint32_t boff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r,
+                                        boff, 0, 0);
+}
+__device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r,
+                                         uint32_t boff, double v) {
+  using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, boff, 0,
+                                        0);
 }
 __device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r,
                                          uint32_t boff, double2 v) {
