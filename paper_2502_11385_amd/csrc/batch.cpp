@@ -100,6 +100,7 @@ std::string build_program(const qsv_variant* vars, size_t count, int b,
   std::iota(hp->order.begin(), hp->order.end(), 0);
   std::stable_sort(hp->order.begin(), hp->order.end(),
                    [&](int a, int c) { return cost[a] > cost[c]; });
+  finalize_program(hp);
   return "";
 }
 
@@ -150,16 +151,65 @@ std::string append_variant(int w, const std::vector<HostGate>& G, int b,
     if (hp->out_offsets.empty()) hp->out_offsets.push_back(0);
     bc.out_offset = hp->out_offsets[i];
     hp->out_offsets.push_back(hp->out_offsets[i] + (uint64_t(1) << w));
-    if (bc.n_passes > 1)
-      hp->slot_amps = std::max(hp->slot_amps, uint64_t(1) << w);
-    else
-      hp->single_tile++;
+    if (bc.n_passes == 1) hp->single_tile++;
     hp->amp_updates += (uint64_t(1) << w) * G.size();
     if (cost)
       *cost = double(uint64_t(1) << w) * (double(G.size()) + 4.0 * bc.n_passes);
     hp->circs.push_back(bc);
   }
   return "";
+}
+
+void finalize_program(HostProgram* hp) {
+  const size_t n = hp->circs.size();
+  std::vector<int32_t> ord = hp->order;
+  if (ord.size() != n) {
+    ord.resize(n);
+    std::iota(ord.begin(), ord.end(), 0);
+  }
+  // states of multi-pass variants, one after another
+  hp->state_amps = 0;
+  int phases = 0;
+  for (BatchCircuit& c : hp->circs) {
+    c.state_offset = 0;
+    if (c.n_passes > 1) {
+      c.state_offset = hp->state_amps;
+      hp->state_amps += uint64_t(1) << c.w;
+    }
+    phases = std::max(phases, int(c.n_passes));
+  }
+  // phase p: pass p of every variant that has one, in the given order
+  hp->work.clear();
+  hp->phase_work_begin.assign(1, 0);
+  hp->phase_tiles.clear();
+  hp->phase_cost.clear();
+  for (int p = 0; p < phases; ++p) {
+    uint64_t tiles = 0, cost = 0;
+    for (int32_t ci : ord) {
+      const BatchCircuit& c = hp->circs[ci];
+      if (p >= c.n_passes) continue;
+      const TilePass& tp = hp->passes[c.pass_begin + p];
+      // a tile's cost: its ops, plus one per segment change and one for
+      // the HBM transfers
+      uint32_t ops = 1;
+      for (int k = 0; k < tp.nseg; ++k) {
+        const TileSeg& sg = hp->segs[tp.seg_begin + k];
+        ops += uint32_t(sg.op_end - sg.op_begin) + 1;
+      }
+      BatchWork wk = {};
+      wk.circ = ci;
+      wk.tile_cost = ops;
+      wk.tile_begin = tiles;
+      wk.cost_begin = cost;
+      hp->work.push_back(wk);
+      const uint64_t nt = uint64_t(1) << (c.w - tp.L);
+      tiles += nt;
+      cost += nt * ops;
+    }
+    hp->phase_work_begin.push_back(hp->work.size());
+    hp->phase_tiles.push_back(tiles);
+    hp->phase_cost.push_back(cost);
+  }
 }
 
 }  // namespace qsv
@@ -187,7 +237,7 @@ struct qsv_batch_s {
   bool use_graph = false;
   HostProgram hp;
   char* prog = nullptr;
-  size_t o_circ = 0, o_order = 0, o_pass = 0, o_seg = 0, o_op = 0;
+  size_t o_circ = 0, o_work = 0, o_pass = 0, o_seg = 0, o_op = 0;
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
   hipGraph_t graph = nullptr;
@@ -225,7 +275,7 @@ qsv_status upload_program(qsv_batch b, const qsv_variant* vars, int L, int RB) {
   }
   std::vector<char> buf;
   b->o_circ = put(buf, b->hp.circs);
-  b->o_order = put(buf, b->hp.order);
+  b->o_work = put(buf, b->hp.work);
   b->o_pass = put(buf, b->hp.passes);
   b->o_seg = put(buf, b->hp.segs);
   b->o_op = put(buf, b->hp.ops);
@@ -236,7 +286,7 @@ qsv_status upload_program(qsv_batch b, const qsv_variant* vars, int L, int RB) {
   }
   he = hipMemcpy(b->prog, buf.data(), buf.size(), hipMemcpyHostToDevice);
   if (he != hipSuccess) return set_error(QSV_ERR_DEVICE, hipGetErrorString(he));
-  b->scratch_bytes = size_t(b->grid) * b->hp.slot_amps * size_t(b->b);
+  b->scratch_bytes = size_t(b->hp.state_amps) * size_t(b->b);
   if (b->scratch_bytes) {
     if (hipMalloc(&b->scratch, b->scratch_bytes) != hipSuccess) {
       b->scratch = nullptr;
@@ -251,12 +301,11 @@ hipError_t launch_direct(qsv_batch b, void* out) {
   return launch_batch(
       b->prec, b->out_fp64, b->RB,
       reinterpret_cast<const BatchCircuit*>(b->prog + b->o_circ),
-      reinterpret_cast<const int32_t*>(b->prog + b->o_order),
-      int32_t(b->count),
       reinterpret_cast<const TilePass*>(b->prog + b->o_pass),
       reinterpret_cast<const TileSeg*>(b->prog + b->o_seg),
-      reinterpret_cast<const TileOp*>(b->prog + b->o_op), out, b->scratch,
-      b->hp.slot_amps, b->L, b->grid, b->stream);
+      reinterpret_cast<const TileOp*>(b->prog + b->o_op),
+      reinterpret_cast<const BatchWork*>(b->prog + b->o_work), b->hp, out,
+      b->scratch, b->L, b->grid, b->stream);
 }
 
 }  // namespace

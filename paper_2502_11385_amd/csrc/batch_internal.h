@@ -23,9 +23,18 @@ struct HostProgram {
   std::vector<TileSeg> segs;
   std::vector<TileOp> ops;
   std::vector<uint64_t> out_offsets;  // circs.size() + 1 entries
-  uint64_t slot_amps = 0;
   uint64_t tiles = 0, amp_updates = 0, single_tile = 0;
+  // filled by finalize_program: phase runs, and the state buffer layout
+  std::vector<BatchWork> work;
+  std::vector<uint64_t> phase_work_begin;  // phases + 1 entries
+  std::vector<uint64_t> phase_tiles;       // tiles per phase
+  std::vector<uint64_t> phase_cost;        // summed tile cost per phase
+  uint64_t state_amps = 0;
 };
+
+// Lay out the states of multi-pass variants and list each phase's tile
+// runs (variants in hp->order, or in index order when it is empty).
+void finalize_program(HostProgram* hp);
 
 // Plan one variant (validated gates G on w qubits, started in |0...0>) and
 // append it to hp; *cost (may be null) receives its estimated work.
@@ -42,11 +51,14 @@ inline bool batchable(const std::vector<HostGate>& G) {
 // Resident work-groups per CU of the batch kernel (0 if the query fails).
 int batch_blocks_per_cu(int prec, int out_fp64, int rb, int L);
 
-hipError_t launch_batch(int prec, int out_fp64, int rb, const BatchCircuit* circs,
-                        const int32_t* order, int32_t count,
-                        const TilePass* passes, const TileSeg* segs,
-                        const TileOp* ops, void* out, void* scratch,
-                        uint64_t slot_amps, int L, int grid,
+// Launch every phase of a finalized batch program on `stream`: phase p
+// runs on min(grid, phase_tiles[p]) work-groups.  `states` holds
+// hp.state_amps amplitudes; `work` is hp.work on the device.
+hipError_t launch_batch(int prec, int out_fp64, int rb,
+                        const BatchCircuit* circs, const TilePass* passes,
+                        const TileSeg* segs, const TileOp* ops,
+                        const BatchWork* work, const HostProgram& hp,
+                        void* out, void* states, int L, int grid,
                         hipStream_t stream);
 
 }  // namespace qsv

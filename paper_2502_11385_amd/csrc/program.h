@@ -115,6 +115,20 @@ struct alignas(16) BatchCircuit {
   int32_t pass_begin;
   int32_t pad;
   uint64_t out_offset;
+  uint64_t state_offset;  // its state in the batch's state buffer (variants
+                          // of more than one pass)
+};
+
+// Phase p of a batch runs pass p of every variant that has one; its tiles
+// are listed as runs, one per variant: entry k covers the phase's tiles
+// tile_begin(k) .. tile_begin(k+1) - 1, which are the tiles of that pass.
+// Work-groups take equal shares of the phase's summed tile cost.
+struct alignas(16) BatchWork {
+  int32_t circ;
+  uint32_t tile_cost;    // estimated cost of one of its tiles
+  uint64_t tile_begin;
+  uint64_t cost_begin;   // summed cost of the phase's tiles before it
+  uint64_t pad;
 };
 
 }  // namespace qsv

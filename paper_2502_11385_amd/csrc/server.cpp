@@ -8,6 +8,7 @@
 // persistent batch launch; wide ones get their own state.  Each group runs
 // on one of a few streams and is retired by polling its event, so new work
 // is admitted and launched while earlier work is still on the device.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -217,6 +218,24 @@ void fail_group(Group* g, const std::string& msg) {
   }
 }
 
+// Resident work-groups of the batch kernel on this device (cached).
+int batch_grid(int prec, int RB, int L) {
+  static int cache[3][6][14] = {};
+  int& g = cache[prec][RB][L];
+  if (!g) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                              dev) != hipSuccess) {
+      (void)hipGetLastError();
+      cus = 1;
+    }
+    g = std::max(1, batch_blocks_per_cu(prec, prec == QSV_C128, RB, L)) *
+        std::max(1, cus);
+  }
+  return g;
+}
+
 // Launch one group of batch-slot requests (same precision).
 void launch_batched(qsv_server s, Group* g, int prec) {
   const int b = prec == QSV_C64 ? 8 : 16;
@@ -231,15 +250,14 @@ void launch_batched(qsv_server s, Group* g, int prec) {
       return;
     }
   }
-  hp.order.resize(hp.circs.size());
-  for (size_t i = 0; i < hp.order.size(); ++i) hp.order[i] = int32_t(i);
+  finalize_program(&hp);  // variants in submission order
   std::vector<char> img;
-  const size_t o_c = put_vec(img, hp.circs), o_o = put_vec(img, hp.order),
+  const size_t o_c = put_vec(img, hp.circs), o_w = put_vec(img, hp.work),
                o_p = put_vec(img, hp.passes), o_s = put_vec(img, hp.segs),
                o_op = put_vec(img, hp.ops);
-  const int grid = int(hp.circs.size());
+  const int grid = batch_grid(prec, RB, L);
   const size_t outb = size_t(hp.out_offsets.back()) * (b == 8 ? 4 : 8);
-  const size_t scrb = size_t(grid) * hp.slot_amps * size_t(b);
+  const size_t scrb = size_t(hp.state_amps) * size_t(b);
   void* hstage = s->hpool.get(img.size());
   char* prog = static_cast<char*>(s->dpool.get(img.size()));
   void* out = s->dpool.get(outb);
@@ -258,11 +276,11 @@ void launch_batched(qsv_server s, Group* g, int prec) {
   if (e == hipSuccess)
     e = launch_batch(prec, b == 16, RB,
                      reinterpret_cast<const BatchCircuit*>(prog + o_c),
-                     reinterpret_cast<const int32_t*>(prog + o_o), grid,
                      reinterpret_cast<const TilePass*>(prog + o_p),
                      reinterpret_cast<const TileSeg*>(prog + o_s),
-                     reinterpret_cast<const TileOp*>(prog + o_op), out, scr,
-                     hp.slot_amps, L, grid, st);
+                     reinterpret_cast<const TileOp*>(prog + o_op),
+                     reinterpret_cast<const BatchWork*>(prog + o_w), hp, out,
+                     scr, L, grid, st);
   for (size_t i = 0; i < g->reqs.size() && e == hipSuccess; ++i) {
     Req* r = g->reqs[i];
     const size_t esz = b == 8 ? 4 : 8;
