@@ -97,6 +97,7 @@ EPILOGUE = {"I": [], "X": ["h"], "Y": ["sdg", "h"]}
 
 
 CUT_WIDTHS, CUT_DEPTH, CUT_SEED = (10, 12, 10), 20, 30
+PLAIN_C128_SAMPLE = 256
 
 
 def cut_leg(qsv, torch, np, steps: int) -> dict:
@@ -144,6 +145,32 @@ def cut_leg(qsv, torch, np, steps: int) -> dict:
            "sum_p": total}
     del rec, vout, ws
     torch.cuda.empty_cache()
+    return res
+
+
+def plans_leg(qsv, torch, np, circ, n: int) -> dict:
+    """The 30-qubit depth-40 circuit under each plan and both precisions:
+    passes, circuit time (sum of pass times, HIP events) and the mean
+    algorithmic GB/s per pass."""
+    res = {}
+    for pname, prec in (("c64", qsv.QSV_C64), ("c128", qsv.QSV_C128)):
+        s = qsv.State(n, prec, stream=torch.cuda.current_stream())
+        s.set_profiling(True)
+        for sname, strat in (("plain", qsv.PLAN_PLAIN),
+                             ("fused", qsv.PLAN_FUSED),
+                             ("tiled", qsv.PLAN_TILED)):
+            s.init_basis(0)
+            s.apply_fused(circ, qsv.fuse_opts(strategy=strat))
+            s.sync()
+            ms, _ = s.pass_times()
+            st = s.plan_stats()
+            tot = float(ms.sum())
+            res[f"{sname}_{pname}"] = {
+                "passes": st["passes"], "circuit_ms": round(tot, 2),
+                "mean_pass_GBps": round(st["alg_bytes"] / (tot * 1e-3) / 1e9,
+                                        1)}
+        s.free()
+        torch.cuda.empty_cache()
     return res
 
 
@@ -207,6 +234,31 @@ def batch_leg(qsv, torch, np, steps: int, per_circuit: bool) -> dict:
         res["per_circuit_s"] = round(t4 - t3, 3)
         res["per_circuit_circuits_per_s"] = round(BATCH_COUNT / (t4 - t3), 1)
         res["speedup_vs_per_circuit"] = round((t4 - t3) / (ms * 1e-3), 2)
+        # plain per-gate complex128, one circuit at a time, on a sample
+        sample = vs[:PLAIN_C128_SAMPLE]
+        st128 = {w: qsv.State(w, qsv.QSV_C128,
+                              stream=torch.cuda.current_stream())
+                 for w in sorted({v.width for v in sample})}
+        out128 = torch.empty(int(offs[len(sample)]), dtype=torch.float64,
+                             device="cuda")
+        plain = qsv.fuse_opts(strategy=qsv.PLAN_PLAIN)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        for i, v in enumerate(sample):
+            s = st128[v.width]
+            s.init_basis(0)
+            s.apply_fused(circs[i], plain)
+            s.probabilities_into(out128.data_ptr() + 8 * int(offs[i]), True)
+        torch.cuda.synchronize()
+        t6 = time.perf_counter()
+        rate128 = len(sample) / (t6 - t5)
+        res["plain_c128_sample"] = len(sample)
+        res["plain_c128_circuits_per_s"] = round(rate128, 1)
+        res["speedup_vs_plain_c128"] = round(
+            BATCH_COUNT / (ms * 1e-3) / rate128, 1)
+        for s in st128.values():
+            s.free()
+        del out128
         for s in states.values():
             s.free()
     del out
@@ -264,15 +316,18 @@ def serve_leg(qsv, n: int) -> dict:
     """Poisson request stream (widths 8..28, depths 10..100, c64 80 %,
     probability vector or 1e4 samples): serial per-request execution
     against continuous batching, on the same seeded trace replayed at
-    0.8 and 2 times the serial service rate."""
+    0.8 and 2 times the serial service rate of those requests."""
     import numpy as np
     from circuits import layered_circuit, serve_trace
     reqs = serve_trace(n + 100, rate_per_s=1.0, seed=5)
     circs = [qsv.Circuit.from_gates(layered_circuit(r.width, r.depth, r.seed))
              for r in reqs]
-    # calibrate the serial service rate on 100 warm-up requests
-    warm = _replay(qsv, reqs[:100], circs[:100], [0.0] * 100, True)
-    mu = warm["circuits_per_s"]
+    # warm up on 100 other requests of the trace, then take the serial
+    # service rate of the replayed requests themselves (all submitted at
+    # once), so that 0.8x is below and 2x above what serial serving sustains
+    _replay(qsv, reqs[:100], circs[:100], [0.0] * 100, True)
+    mu = _replay(qsv, reqs[100:], circs[100:], [0.0] * n, True)[
+        "circuits_per_s"]
     base = np.array([r.arrival_s for r in reqs[100:]])
     base = base - base[0]
     out = {"workload": (f"{n} requests, widths 8..28, depths 10..100, "
@@ -315,6 +370,8 @@ def main() -> int:
                     help="skip the one-call-per-circuit batch baseline")
     ap.add_argument("--no-cut", action="store_true",
                     help="skip the cut-and-reconstruct leg")
+    ap.add_argument("--no-plans", action="store_true",
+                    help="skip the plain/fused/tiled x c64/c128 comparison")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the request-serving leg")
     ap.add_argument("--serve-n", type=int, default=300,
@@ -494,6 +551,8 @@ def main() -> int:
     state.free()
     del probs
     torch.cuda.empty_cache()
+    if not a.no_plans:
+        out["plans"] = plans_leg(qsv, torch, np, circ, n)
     if not a.no_cut:
         out["cut"] = cut_leg(qsv, torch, np, max(1, a.steps))
     if not a.no_batch:

@@ -401,14 +401,31 @@ void scheduler(qsv_server s) {
       finish(s, g);
       progress = true;
     }
-    // 2. admit first-come first-served while the budget allows
+    // 2. admit first-come first-served while the budget allows and the
+    // requests form no more groups than there are idle streams (one group
+    // per stream: requests overlap on the device without the whole backlog
+    // sharing it, which would delay every request)
     std::vector<Req*> ready;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      const bool may = !s->o.serial || s->running.empty();
-      while (may && !s->pending.empty() &&
+      const size_t slots =
+          s->o.serial ? (s->running.empty() ? 1 : 0)
+                      : (s->running.size() < size_t(s->o.n_streams)
+                             ? size_t(s->o.n_streams) - s->running.size()
+                             : 0);
+      size_t groups = 0;
+      int in_batch[3] = {0, 0, 0};  // requests in the open batch group
+      while (!s->pending.empty() &&
              s->reserved + s->pending.front()->need <= s->o.budget_bytes) {
         Req* r = s->pending.front();
+        const bool opens = !r->batched || in_batch[r->prec] == 0 ||
+                           in_batch[r->prec] >= s->o.max_batch;
+        if (opens && groups + 1 > slots) break;
+        if (opens) {
+          ++groups;
+          if (r->batched) in_batch[r->prec] = 0;
+        }
+        if (r->batched) ++in_batch[r->prec];
         s->pending.pop_front();
         r->t_admit = now_s();
         s->reserved += r->need;
@@ -457,8 +474,19 @@ void scheduler(qsv_server s) {
           g->reqs.push_back(r);
           groups.push_back(g);
         }
+      std::vector<char> busy(s->o.n_streams, 0);
+      for (Group* g : s->running) busy[g->stream_idx] = 1;
       for (Group* g : groups) {
-        g->stream_idx = s->rr++ % s->o.n_streams;
+        // an idle stream (round-robin among them), else the next one
+        int pick = -1;
+        for (int k = 0; k < s->o.n_streams && pick < 0; ++k) {
+          const int c = (s->rr + k) % s->o.n_streams;
+          if (!busy[c]) pick = c;
+        }
+        if (pick < 0) pick = s->rr % s->o.n_streams;
+        s->rr = pick + 1;
+        busy[pick] = 1;
+        g->stream_idx = pick;
         const double t = now_s();
         for (Req* r : g->reqs) r->t_start = t;
         if (g->reqs[0]->batched)
