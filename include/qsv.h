@@ -124,7 +124,7 @@ typedef enum {
 
 /* Options of qsv_apply_fused; all-zero (or NULL) selects defaults.
  *   tile_log2  : tile size L (amplitudes per tile = 2^L), 8..13, with
- *                L - reg_log2 <= 9 (default 12 for c64, 11 for c128)
+ *                L - reg_log2 <= 9 (default 12)
  *   k_max      : widest fused block, 1..5 (default 5)
  *   low_qubits : qubits 0..low_qubits-1 belong to every tile so that HBM
  *                accesses are contiguous runs (default 5 c64, 4 c128)

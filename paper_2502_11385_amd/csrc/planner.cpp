@@ -23,7 +23,7 @@ std::string resolve_options(int n, int bytes_per_amp, const int* v,
                             PlanOptions* o) {
   PlanOptions r;
   r.strategy = v ? v[0] : 0;
-  r.tile_log2 = (v && v[1]) ? v[1] : (bytes_per_amp == 8 ? 12 : 11);
+  r.tile_log2 = (v && v[1]) ? v[1] : 12;
   r.k_max = (v && v[2]) ? v[2] : 5;
   r.low_qubits = (v && v[3]) ? v[3] : (bytes_per_amp == 8 ? 5 : 4);
   r.reg_log2 = (v && v[4]) ? v[4] : 4;
