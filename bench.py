@@ -174,6 +174,49 @@ def plans_leg(qsv, torch, np, circ, n: int) -> dict:
     return res
 
 
+WIDE = ((34, "c64", 34), (33, "c128", 33))   # (qubits, precision, seed)
+
+
+def wide_leg(qsv, torch, np) -> dict:
+    """The widest states one GPU holds (128 GiB each): 34 qubits complex64
+    and 33 qubits complex128, a QFT ladder on a random basis state followed
+    by 10 layered U3+CZ layers, then the marginal of the top 10 qubits and
+    10^6 samples.  Per precision: the planned passes, the circuit time (sum
+    of pass times, HIP events, second of two runs) and its mean algorithmic
+    GB/s, and the output times."""
+    from circuits import qft_style_circuit
+    res = {}
+    for n, pname, seed in WIDE:
+        prec = qsv.QSV_C64 if pname == "c64" else qsv.QSV_C128
+        x, gates = qft_style_circuit(n, seed)
+        circ = qsv.Circuit.from_gates(gates)
+        s = qsv.State(n, prec, stream=torch.cuda.current_stream())
+        s.set_profiling(True)
+        tot = 0.0
+        for _ in range(2):
+            s.init_basis(x)
+            s.apply_fused(circ)
+            s.sync()
+            ms, _ = s.pass_times()
+            tot = float(ms.sum())
+        st = s.plan_stats()
+        t0 = time.perf_counter()
+        marg = s.marginal(list(range(n - 10, n)))
+        t1 = time.perf_counter()
+        s.sample(SHOTS, SAMPLE_SEED)
+        t2 = time.perf_counter()
+        res[f"{n}q_{pname}"] = {
+            "gates": len(gates), "passes": st["passes"],
+            "circuit_ms": round(tot, 1),
+            "mean_pass_GBps": round(st["alg_bytes"] / (tot * 1e-3) / 1e9, 1),
+            "marginal_ms": round((t1 - t0) * 1e3, 2),
+            "samples_ms": round((t2 - t1) * 1e3, 2),
+            "marginal_sum": float(np.sum(marg))}
+        s.free()
+        torch.cuda.empty_cache()
+    return res
+
+
 def batch_leg(qsv, torch, np, steps: int, per_circuit: bool) -> dict:
     """4096 cut variants (widths 10..20, depths 10..60), complex64: one
     persistent launch (autotuned, replayed from a hipGraph) against one
@@ -372,6 +415,8 @@ def main() -> int:
                     help="skip the cut-and-reconstruct leg")
     ap.add_argument("--no-plans", action="store_true",
                     help="skip the plain/fused/tiled x c64/c128 comparison")
+    ap.add_argument("--no-wide", action="store_true",
+                    help="skip the 34-qubit / 33-qubit QFT-style leg")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the request-serving leg")
     ap.add_argument("--serve-n", type=int, default=300,
@@ -553,6 +598,8 @@ def main() -> int:
     torch.cuda.empty_cache()
     if not a.no_plans:
         out["plans"] = plans_leg(qsv, torch, np, circ, n)
+    if not a.no_wide:
+        out["wide"] = wide_leg(qsv, torch, np)
     if not a.no_cut:
         out["cut"] = cut_leg(qsv, torch, np, max(1, a.steps))
     if not a.no_batch:

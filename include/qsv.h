@@ -153,7 +153,10 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
  *   out[0] passes launched, out[1] gates, out[2] algorithmic HBM bytes
  *   (sum over passes of bytes read + written), out[3] tile passes,
  *   out[4] plain passes, out[5] fused passes, out[6] tile segments,
- *   out[7] host planning time in nanoseconds.  n_out <= 8 entries. */
+ *   out[7] host planning time in nanoseconds, out[8] tile ops,
+ *   out[9] phase blocks (runs of diagonal gates applied as one phase
+ *   polynomial), out[10] diagonal gates inside phase blocks.
+ *   n_out <= 11 entries. */
 qsv_status qsv_last_plan_stats(qsv_state s, uint64_t* out, int32_t n_out);
 
 /* Per-pass timing.  While enabled (enable != 0), qsv_apply_fused records
@@ -179,6 +182,15 @@ qsv_status qsv_plan_describe(const qsv_circuit* circ, int32_t n_qubits,
                              int32_t* gate_pass, int32_t* gate_order,
                              int32_t* pass_kind, uint64_t* pass_qubits,
                              int32_t* n_passes);
+
+/* Host-only dry run of the device program (no device work): plans the
+ * circuit as qsv_apply_fused would and builds its tile programs, then
+ * writes out[0] passes, out[1] tile passes, out[2] tile segments,
+ * out[3] tile ops, out[4] phase blocks, out[5] diagonal gates inside
+ * phase blocks.  n_out <= 6 entries. */
+qsv_status qsv_plan_program_stats(const qsv_circuit* circ, int32_t n_qubits,
+                                  int32_t prec, const qsv_fuse_opts* opts,
+                                  uint64_t* out, int32_t n_out);
 
 /* Testing aid (host only, no device work): plan the circuit with the
  * tiled strategy for n_qubits <= 16, build the exact device program the

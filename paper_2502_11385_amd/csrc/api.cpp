@@ -39,7 +39,7 @@ struct qsv_state_s {
   // reduction scratch
   char* scratch = nullptr;
   size_t scratch_cap = 0;
-  uint64_t stats[8] = {0};
+  uint64_t stats[11] = {0};
   // per-pass timing
   bool profiling = false;
   std::vector<hipEvent_t> evs;
@@ -385,6 +385,7 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
   std::vector<TilePass> tpasses;
   std::vector<TileSeg> tsegs;
   std::vector<TileOp> tops;
+  TileEmitStats est;
   std::vector<FusedBlock> fblocks;
   std::vector<FusedGate> fgates;
   std::vector<double> mats;             // gate matrices (FP64)
@@ -395,7 +396,7 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
     const Pass& p = plan.passes[pi];
     if (p.kind == kPassTile) {
       std::string err = emit_tile_pass(p, G, po.reg_log2, &tpasses, &tsegs,
-                                       &tops);
+                                       &tops, &est);
       if (!err.empty()) return fail(QSV_ERR_DEVICE, err);
     } else if (p.kind == kPassPlain) {
       const HostGate& g = G[p.gates[0]];
@@ -517,6 +518,9 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
   s->stats[6] = uint64_t(plan.segments);
   s->stats[7] = uint64_t(
       std::chrono::duration_cast<std::chrono::nanoseconds>(t1 - t0).count());
+  s->stats[8] = est.ops;
+  s->stats[9] = est.blocks;
+  s->stats[10] = est.block_gates;
   return QSV_OK;
 }
 
@@ -549,7 +553,7 @@ qsv_status qsv_pass_times(qsv_state s, float* ms_out, int32_t* kinds_out,
 
 qsv_status qsv_last_plan_stats(qsv_state s, uint64_t* out, int32_t n_out) {
   if (!s) return fail(QSV_ERR_INVALID_ARG, "null state");
-  if (!out || n_out < 0 || n_out > 8)
+  if (!out || n_out < 0 || n_out > 11)
     return fail(QSV_ERR_INVALID_ARG, "bad stats buffer");
   for (int i = 0; i < n_out; ++i) out[i] = s->stats[i];
   return QSV_OK;
@@ -582,6 +586,35 @@ qsv_status qsv_plan_describe(const qsv_circuit* circ, int32_t n, int32_t prec,
     }
   }
   *n_passes = int32_t(plan.passes.size());
+  return QSV_OK;
+}
+
+qsv_status qsv_plan_program_stats(const qsv_circuit* circ, int32_t n,
+                                  int32_t prec, const qsv_fuse_opts* opts,
+                                  uint64_t* out, int32_t n_out) {
+  if (prec != QSV_C64 && prec != QSV_C128)
+    return fail(QSV_ERR_UNSUPPORTED, "unknown precision");
+  if (n < 1 || n > QSV_MAX_QUBITS)
+    return fail(QSV_ERR_INVALID_ARG, "n_qubits must be 1..34");
+  if (!out || n_out < 0 || n_out > 6)
+    return fail(QSV_ERR_INVALID_ARG, "bad stats buffer");
+  std::vector<HostGate> G;
+  PlanOptions po;
+  Plan plan;
+  qsv_status st = plan_for(circ, n, prec, opts, &G, &po, &plan);
+  if (st != QSV_OK) return st;
+  std::vector<TilePass> tp;
+  std::vector<TileSeg> ts;
+  std::vector<TileOp> to;
+  TileEmitStats est;
+  for (const Pass& p : plan.passes) {
+    if (p.kind != kPassTile) continue;
+    std::string err = emit_tile_pass(p, G, po.reg_log2, &tp, &ts, &to, &est);
+    if (!err.empty()) return fail(QSV_ERR_DEVICE, err);
+  }
+  const uint64_t v[6] = {plan.passes.size(), tp.size(), ts.size(), est.ops,
+                         est.blocks, est.block_gates};
+  for (int i = 0; i < n_out; ++i) out[i] = v[i];
   return QSV_OK;
 }
 
@@ -679,6 +712,33 @@ qsv_status qsv_debug_emulate_tiled(const qsv_circuit* circ, int32_t n,
                   m10(m[4], m[5]), m11(m[6], m[7]);
               put(gidx(r), m00 * x0 + m01 * x1);
               put(gidx(r1), m10 * x0 + m11 * x1);
+            } else if (op.kind == kOpPhaseBlock) {
+              const int RB = po.reg_log2;
+              const PhaseBlock* pb = reinterpret_cast<const PhaseBlock*>(
+                  reinterpret_cast<const char*>(&op) + op.blob);
+              const PhaseTerm* t = reinterpret_cast<const PhaseTerm*>(pb + 1);
+              uint32_t regmask = 0, j = 0;
+              for (int i = 0; i < RB; ++i) {
+                regmask |= 1u << sg.reg_bits[i];
+                j |= ((r >> sg.reg_bits[i]) & 1u) << i;
+              }
+              const uint32_t thr = r & ~regmask;
+              uint64_t sum = 0;
+              for (int k = 0; k <= RB; ++k) {
+                const bool reg_on = k == 0 || (j >> (k - 1) & 1);
+                for (int i = 0; i < pb->n_uni[k] + pb->n_thr[k]; ++i, ++t) {
+                  if ((t->tmask == 0) != (i < pb->n_uni[k]) || (t->tmask & regmask))
+                    return fail(QSV_ERR_DEVICE, "inconsistent phase block");
+                  if (reg_on && (base & t->gmask) == t->gmask &&
+                      (thr & t->tmask) == t->tmask)
+                    sum += t->turns;
+                }
+              }
+              const double ang = std::ldexp(double(sum), -64) * 2.0 * M_PI;
+              std::complex<double> f(std::cos(ang), std::sin(ang));
+              if (pb->has_table)
+                f *= std::complex<double>(pb->td[2 * j], pb->td[2 * j + 1]);
+              put(gidx(r), C(gidx(r)) * f);
             } else if (op.kind == kOpPhase) {
               put(gidx(r), C(gidx(r)) * std::complex<double>(op.m[0], op.m[1]));
             } else {

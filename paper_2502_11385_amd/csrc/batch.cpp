@@ -189,12 +189,14 @@ void finalize_program(HostProgram* hp) {
       const BatchCircuit& c = hp->circs[ci];
       if (p >= c.n_passes) continue;
       const TilePass& tp = hp->passes[c.pass_begin + p];
-      // a tile's cost: its ops, plus one per segment change and one for
-      // the HBM transfers
+      // a tile's cost: its ops (a phase block as three), plus one per
+      // segment change and one for the HBM transfers
       uint32_t ops = 1;
       for (int k = 0; k < tp.nseg; ++k) {
         const TileSeg& sg = hp->segs[tp.seg_begin + k];
-        ops += uint32_t(sg.op_end - sg.op_begin) + 1;
+        for (int oi = sg.op_begin; oi < sg.op_end; ++oi)
+          ops += hp->ops[oi].kind == kOpPhaseBlock ? 3 : 1;
+        ops += 1;
       }
       BatchWork wk = {};
       wk.circ = ci;

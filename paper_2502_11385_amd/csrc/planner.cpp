@@ -14,6 +14,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <tuple>
 
 namespace qsv {
 
@@ -248,10 +250,51 @@ static void diag_value(const HostGate& d, uint64_t bits, double* re,
   *im = d.m[2 * (r * dim + r) + 1];
 }
 
+// Phase terms of a diagonal unitary gate.  Its phase function over the
+// target bits, phi(r) = arg of diagonal entry r, has a unique multilinear
+// expansion phi(r) = sum over target subsets S of c_S * [all bits of S set
+// in r]; the coefficients are the Moebius inversion c_S = sum over T within
+// S of (-1)^{|S|-|T|} phi(T).  Each nonzero c_S becomes a term whose mask is
+// S's qubits plus the controls.  False when an entry is not of unit modulus
+// (then the gate is not a phase and keeps its own op).
+static bool phase_terms(const HostGate& g,
+                        std::vector<std::pair<uint64_t, double>>* out) {
+  const int d = 1 << g.k;
+  double phi[1 << kMaxK];
+  for (int r = 0; r < d; ++r) {
+    const double re = g.m[2 * (r * d + r)], im = g.m[2 * (r * d + r) + 1];
+    if (std::fabs(std::hypot(re, im) - 1.0) > 1e-12) return false;
+    phi[r] = std::atan2(im, re);
+  }
+  for (int j = 0; j < g.k; ++j)
+    for (int S = 0; S < d; ++S)
+      if (S >> j & 1) phi[S] -= phi[S ^ (1 << j)];
+  for (int S = 0; S < d; ++S) {
+    if (std::fabs(phi[S]) < 1e-15) continue;
+    uint64_t mask = g.cmask;
+    for (int j = 0; j < g.k; ++j)
+      if (S >> j & 1) mask |= uint64_t(1) << g.t[j];
+    out->push_back({mask, phi[S]});
+  }
+  return true;
+}
+
+// An angle as a fixed-point fraction of a turn: round(angle / 2pi * 2^64)
+// modulo 2^64.
+static uint64_t angle_turns(double ang) {
+  double f = ang / (2.0 * M_PI);
+  f -= std::floor(f);  // [0, 1]
+  const double x = std::ldexp(f, 32);
+  const double hi = std::floor(x);
+  const uint64_t lo = uint64_t(std::llround(std::ldexp(x - hi, 32)));
+  return (uint64_t(hi) << 32) + lo;  // wraps modulo 2^64
+}
+
 std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
                            int RB, std::vector<TilePass>* tpasses,
                            std::vector<TileSeg>* tsegs,
-                           std::vector<TileOp>* tops) {
+                           std::vector<TileOp>* tops,
+                           TileEmitStats* stats) {
   TilePass tp = {};
   tp.L = p.L;
   tp.nseg = int32_t(p.segs.size());
@@ -336,6 +379,122 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
     op_target_q.push_back(-1);
     touch_op(g.touch(), int(tops->size()) - 1);
   };
+  // Runs of diagonal gates: those whose phase terms all fit the segment's
+  // layout (at most one register bit per term, or register bits only)
+  // become one kOpPhaseBlock when there are at least kMinBlock of them; the
+  // others keep an op each.  Diagonal gates commute, so the order of the
+  // block and the single ops does not matter.
+  constexpr size_t kMinBlock = 4;
+  struct Blob {
+    int op;
+    std::vector<char> bytes;
+  };
+  std::vector<Blob> blobs;
+  auto emit_diag_run = [&](const std::vector<int>& run, const Pass::Seg& sg) {
+    std::vector<int> blocked, single;
+    // per term: accumulator, thread mask, outer mask -> summed turns
+    std::map<std::tuple<int, uint32_t, uint64_t>, uint64_t> acc;
+    uint64_t table[1 << kMaxRegBits] = {0};
+    std::vector<std::pair<uint64_t, double>> terms;
+    struct Placed {
+      int k;
+      uint32_t tm;
+      uint64_t gm;
+      uint32_t regs;
+      uint64_t turns;
+    };
+    std::vector<std::vector<Placed>> placed(run.size());
+    for (size_t i = 0; i < run.size(); ++i) {
+      const HostGate& g = G[run[i]];
+      terms.clear();
+      bool ok = phase_terms(g, &terms);
+      for (size_t e = 0; ok && e < terms.size(); ++e) {
+        Placed pl = {0, 0u, 0, 0u, angle_turns(terms[e].second)};
+        int nreg = 0, rlast = -1;
+        for (int q = 0; q < 64; ++q) {
+          if (!(terms[e].first >> q & 1)) continue;
+          if (!(p.qubits >> q & 1)) {
+            pl.gm |= uint64_t(1) << q;
+            continue;
+          }
+          const int lb = local_of[q];
+          int r = -1;
+          for (int b = 0; b < RB; ++b)
+            if (sg.reg_bits[b] == lb) r = b;
+          if (r >= 0) {
+            pl.regs |= 1u << r;
+            ++nreg;
+            rlast = r;
+          } else {
+            pl.tm |= 1u << lb;
+          }
+        }
+        if (nreg <= 1) pl.k = nreg ? 1 + rlast : 0;
+        else if (pl.tm == 0 && pl.gm == 0) pl.k = -1;  // register table
+        else ok = false;
+        placed[i].push_back(pl);
+      }
+      (ok ? blocked : single).push_back(int(i));
+    }
+    if (blocked.size() < kMinBlock) {
+      for (int d : run) emit_diag_tracked(G[d]);
+      return;
+    }
+    for (int i : single) emit_diag_tracked(G[run[i]]);
+    if (stats) {
+      stats->blocks++;
+      stats->block_gates += blocked.size();
+    }
+    uint64_t touched = 0;
+    for (int i : blocked) {
+      touched |= G[run[i]].touch();
+      for (const Placed& pl : placed[i]) {
+        if (pl.k >= 0) {
+          acc[std::make_tuple(pl.k, pl.tm, pl.gm)] += pl.turns;
+        } else {
+          for (uint32_t j = 0; j < (1u << RB); ++j)
+            if ((j & pl.regs) == pl.regs) table[j] += pl.turns;
+        }
+      }
+    }
+    PhaseBlock hdr = {};
+    std::vector<PhaseTerm> out;
+    for (const auto& kv : acc) {  // ordered by accumulator, then tmask
+      if (kv.second == 0) continue;
+      const int k = std::get<0>(kv.first);
+      PhaseTerm t = {};
+      t.tmask = std::get<1>(kv.first);
+      t.gmask = std::get<2>(kv.first);
+      t.turns = kv.second;
+      t.turns32 = uint32_t((kv.second + (uint64_t(1) << 31)) >> 32);
+      (t.tmask ? hdr.n_thr : hdr.n_uni)[k]++;
+      out.push_back(t);
+    }
+    for (uint32_t j = 0; j < (1u << RB); ++j) {
+      if (table[j]) hdr.has_table = 1;
+      const double a = std::ldexp(double(table[j]), -64) * 2.0 * M_PI;
+      hdr.td[2 * j] = std::cos(a);
+      hdr.td[2 * j + 1] = std::sin(a);
+      hdr.tf[2 * j] = float(hdr.td[2 * j]);
+      hdr.tf[2 * j + 1] = float(hdr.td[2 * j + 1]);
+    }
+    hdr.n_terms = int32_t(out.size());
+    Blob bl;
+    bl.bytes.resize(sizeof hdr + out.size() * sizeof(PhaseTerm));
+    std::memcpy(bl.bytes.data(), &hdr, sizeof hdr);
+    if (!out.empty())
+      std::memcpy(bl.bytes.data() + sizeof hdr, out.data(),
+                  out.size() * sizeof(PhaseTerm));
+    TileOp op = {};
+    op.kind = kOpPhaseBlock;
+    op.mux = kMuxNone;
+    tops->push_back(op);
+    bl.op = int(tops->size()) - 1;
+    blobs.push_back(std::move(bl));
+    op_mux_q.push_back(-1);
+    op_target_q.push_back(-1);
+    touch_op(touched, int(tops->size()) - 1);
+  };
   std::vector<int> pend;
   for (size_t si = 0; si < p.segs.size(); ++si) {
     const auto& sg = p.segs[si];
@@ -377,7 +536,7 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
         }
       }
       if (!fold) {
-        for (int d : hit) emit_diag_tracked(G[d]);
+        emit_diag_run(hit, sg);
         if (!plain && g.c == 0) mux_q = -1;
         if (!plain && g.c == 1) mux_q = g.ctl[0];
       } else {
@@ -478,7 +637,7 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
       }
     }
     if (si + 1 == p.segs.size()) {
-      for (int d : pend) emit_diag_tracked(G[d]);
+      emit_diag_run(pend, sg);
       pend.clear();
     }
     ts.op_end = int32_t(tops->size());
@@ -497,6 +656,15 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
       if (op.mux_reg == op.reg)
         return "internal planner error: mux bit equals the target bit";
     }
+  }
+  if (stats) stats->ops += tops->size() - size_t(op_base);
+  // Phase-block records follow the pass's ops, in whole TileOp slots.
+  for (const Blob& bl : blobs) {
+    const size_t at = tops->size();
+    const size_t nrec = (bl.bytes.size() + sizeof(TileOp) - 1) / sizeof(TileOp);
+    tops->resize(at + nrec);
+    std::memcpy(static_cast<void*>(&(*tops)[at]), bl.bytes.data(), bl.bytes.size());
+    (*tops)[bl.op].blob = int32_t((at - size_t(bl.op)) * sizeof(TileOp));
   }
   tpasses->push_back(tp);
   return "";

@@ -71,12 +71,22 @@ std::string make_gate(int n, int k, int c, const int32_t* qubits,
 void make_plan(const std::vector<HostGate>& gates, int n, int bytes_per_amp,
                const PlanOptions& opt, Plan* plan);
 
+// Counts of what emit_tile_pass produced (accumulated over calls).
+struct TileEmitStats {
+  uint64_t ops = 0;          // tile ops (phase-block data records excluded)
+  uint64_t blocks = 0;       // kOpPhaseBlock ops
+  uint64_t block_gates = 0;  // diagonal gates applied inside phase blocks
+};
+
 // Append the device records of one tile pass (its TilePass, segments and
-// ops; segment and op indices are global into the output vectors).
+// ops; segment and op indices are global into the output vectors; the
+// pass's phase-block records follow its ops).
+
 std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
                            int reg_log2, std::vector<TilePass>* passes,
                            std::vector<TileSeg>* segs,
-                           std::vector<TileOp>* ops);
+                           std::vector<TileOp>* ops,
+                           TileEmitStats* stats = nullptr);
 
 // Algorithmic bytes of applying gate g as a plain per-gate kernel.
 uint64_t plain_gate_bytes(const HostGate& g, int n, int bytes_per_amp);

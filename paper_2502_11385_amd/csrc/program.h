@@ -15,7 +15,8 @@ constexpr int kMaxTileBits = 14;
 enum : int32_t {
   kOpDense1 = 0,  // 2x2 matrix on one register bit, optional controls
   kOpDiag = 1,    // diagonal table on 1-2 qubits (local or outside the tile)
-  kOpPhase = 2    // multiply by m[0..1] where every bit of a mask is 1
+  kOpPhase = 2,   // multiply by m[0..1] where every bit of a mask is 1
+  kOpPhaseBlock = 3  // a run of diagonal gates as one phase polynomial
 };
 
 // One gate inside a tile segment.
@@ -29,6 +30,9 @@ enum : int32_t {
 //             (CZ, CP, S, T, P, multi-controlled phases): the amplitude is
 //             multiplied by the phase m[0..1] when all its target and
 //             control bits are 1; lctrl/gctrl then hold targets as well.
+//  kOpPhaseBlock: a run of diagonal unitary gates applied as one factor
+//             e^{i phi(x)}, phi a sum of terms; see PhaseBlock.  `blob` is
+//             the byte offset from this op to its PhaseBlock record.
 //  lctrl: controls inside the tile as a mask of tile-local bits.
 //  gctrl: controls outside the tile as a mask of global qubits.
 struct alignas(16) TileOp {
@@ -51,9 +55,44 @@ struct alignas(16) TileOp {
   int32_t mux_reg;
   double m2[8];
   float mf2[8];
+  int32_t blob;  // kOpPhaseBlock only
+  int32_t pad_;
 };
 
 constexpr int32_t kMuxNone = -1000;
+
+// Phase blocks.  A product of diagonal unitary gates is e^{i phi(x)} with
+// phi(x) = sum over terms of angle * [every bit of the term's mask is 1 in
+// x] (mod 2 pi): the multilinear expansion of each gate's phase function.
+// Within a segment every term's mask splits into register bits, thread bits
+// (tile-local, mask `tmask`) and outer qubits (global mask `gmask`); the
+// planner keeps only terms with at most one register bit, plus terms made
+// of register bits alone, which go into a 2^RB-entry table.  Angles are
+// fixed-point fractions of a turn, so that sums wrap exactly modulo 2 pi.
+constexpr int kMaxRegBits = 5;
+
+struct alignas(16) PhaseTerm {
+  uint64_t gmask;    // outer qubits that must be 1
+  uint64_t turns;    // angle / (2 pi) * 2^64, modulo 2^64
+  uint32_t tmask;    // thread bits (tile-local) that must be 1
+  uint32_t turns32;  // turns rounded to 32 bits (complex64)
+  uint32_t pad[2];
+};
+
+// Accumulator 0 holds the terms without a register bit; accumulator 1 + r
+// the terms whose one register bit is register bit r of the segment.  The
+// terms follow the record in accumulator order, each accumulator's terms
+// with tmask == 0 (uniform over a tile) first.
+struct alignas(16) PhaseBlock {
+  int32_t n_uni[kMaxRegBits + 1];  // terms with tmask == 0
+  int32_t n_thr[kMaxRegBits + 1];  // terms with tmask != 0
+  int32_t has_table;               // table below differs from all ones
+  int32_t n_terms;
+  int32_t pad[2];
+  // factor of register index j from terms on register bits only
+  float tf[2 << kMaxRegBits];
+  double td[2 << kMaxRegBits];
+};
 
 // A run of ops executed with one register layout: the tile-local bits in
 // reg_bits[0..RB-1] (ascending) index each thread's registers; the other

@@ -260,6 +260,97 @@ __device__ __forceinline__ void relayout(C* a, C* lds, const Layout<RB>& from,
   __syncthreads();
 }
 
+// e^{2 pi i t / 2^32} for a fixed-point fraction of a turn.  The top 24
+// bits go through sincospi exactly (an int32 with its low 8 bits clear is
+// exact in FP32); the low 8 bits, below 4e-7 rad, enter to first order.
+__device__ __forceinline__ float2 turn_phase32(uint32_t t) {
+  const float y = float(int32_t(t & ~0xFFu)) * 0x1p-31f;
+  float sn, cs;
+  sincospif(y, &sn, &cs);
+  const float d = float(t & 0xFFu) * (3.14159265358979f * 0x1p-31f);
+  return make_float2(__builtin_fmaf(-sn, d, cs), __builtin_fmaf(cs, d, sn));
+}
+
+// e^{2 pi i t / 2^64} in FP64 (the int64 -> double rounding is 2^-53 of a
+// half turn at most).
+__device__ __forceinline__ double2 turn_phase64(uint64_t t) {
+  const double y = double(int64_t(t)) * 0x1p-63;
+  double sn, cs;
+  sincospi(y, &sn, &cs);
+  return make_double2(cs, sn);
+}
+
+// Multiply the register tile by a PhaseBlock's factor.  Per thread, each
+// accumulator sums the angles of its terms whose thread and outer bits are
+// all 1 (terms without thread bits are uniform over the tile); then one
+// phase per accumulator multiplies the registers that carry its register
+// bit, and the register table (terms on register bits only) the rest.
+template <typename T, int RB>
+__device__ __forceinline__ void phase_block(typename CxT<T>::type* a,
+                                            const PhaseBlock* pb, uint32_t rt,
+                                            uint64_t base) {
+  using C = typename CxT<T>::type;
+  using U = typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type;
+  constexpr int R = 1 << RB;
+  const PhaseTerm* t = reinterpret_cast<const PhaseTerm*>(pb + 1);
+  U acc[RB + 1];
+#pragma unroll
+  for (int k = 0; k <= RB; ++k) {
+    U au = 0;
+    const int nu = pb->n_uni[k];
+    for (int i = 0; i < nu; ++i, ++t) {
+      const uint64_t gm = t->gmask;
+      const U w = sizeof(T) == 4 ? U(t->turns32) : U(t->turns);
+      au += (base & gm) == gm ? w : U(0);
+    }
+    U av = 0;
+    const int nv = pb->n_thr[k];
+    for (int i = 0; i < nv; ++i, ++t) {
+      const uint64_t gm = t->gmask;
+      const uint32_t tm = t->tmask;
+      const U w = sizeof(T) == 4 ? U(t->turns32) : U(t->turns);
+      const bool on = ((base & gm) == gm) && ((rt & tm) == tm);
+      av += on ? w : U(0);
+    }
+    acc[k] = au + av;
+  }
+  if (pb->n_uni[0] + pb->n_thr[0] > 0) {
+    C f0;
+    if constexpr (sizeof(T) == 4) f0 = turn_phase32(acc[0]);
+    else f0 = turn_phase64(acc[0]);
+    if (pb->has_table) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        C u;
+        if constexpr (sizeof(T) == 4) u = make_float2(pb->tf[2 * j], pb->tf[2 * j + 1]);
+        else u = make_double2(pb->td[2 * j], pb->td[2 * j + 1]);
+        a[j] = cmul(a[j], cmul(f0, u));
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < R; ++j) a[j] = cmul(a[j], f0);
+    }
+  } else if (pb->has_table) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      C u;
+      if constexpr (sizeof(T) == 4) u = make_float2(pb->tf[2 * j], pb->tf[2 * j + 1]);
+      else u = make_double2(pb->td[2 * j], pb->td[2 * j + 1]);
+      a[j] = cmul(a[j], u);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    if (pb->n_uni[1 + r] + pb->n_thr[1 + r] == 0) continue;
+    C kr;
+    if constexpr (sizeof(T) == 4) kr = turn_phase32(acc[1 + r]);
+    else kr = turn_phase64(acc[1 + r]);
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (j >> r & 1) a[j] = cmul(a[j], kr);
+  }
+}
+
 // Apply every segment of one tile pass to the register tile `a`, which is
 // in the I/O layout on entry and is left in the I/O layout on exit.  `base`
 // is the tile's global index with all tile bits zero (outer controls and
@@ -330,6 +421,12 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
         } else {
           dense1_dispatch<R, false>(op->reg, a, m, rt, lr, lctrl);
         }
+      } else if (kind == kOpPhaseBlock) {
+        phase_block<T, RB>(
+            a,
+            reinterpret_cast<const PhaseBlock*>(
+                reinterpret_cast<const char*>(op) + op->blob),
+            rt, base);
       } else if (kind == kOpPhase) {
         C ph;
         if constexpr (sizeof(T) == 4) {

@@ -50,7 +50,7 @@ EXPORTED = [
     "qsv_batch_stats", "qsv_batch_free", "qsv_gate_matrices",
     "qsv_server_create", "qsv_server_submit", "qsv_server_wait",
     "qsv_server_release", "qsv_server_stats", "qsv_server_destroy",
-    "qsv_clock", "qsv_debug_emulate_tiled",
+    "qsv_clock", "qsv_debug_emulate_tiled", "qsv_plan_program_stats",
     "qsv_cut_workspace_bytes", "qsv_cut_reconstruct",
     "qsv_top_k", "qsv_expectation_pauli", "qsv_permute_qubits",
 ]
@@ -144,6 +144,8 @@ _SIGS = {
     "qsv_gate_matrices": [C.c_char_p, _pd, _i32, C.c_size_t, _pd],
     "qsv_debug_emulate_tiled": [C.POINTER(qsv_circuit), _i32,
                                 C.POINTER(qsv_fuse_opts), _pd],
+    "qsv_plan_program_stats": [C.POINTER(qsv_circuit), _i32, _i32,
+                               C.POINTER(qsv_fuse_opts), _pu64, _i32],
     "qsv_probabilities": [_p, _p, _i32],
     "qsv_norm": [_p, _pd],
     "qsv_renormalize": [_p, _pd],
@@ -335,6 +337,20 @@ def plan_describe(circ: Circuit, n: int, prec: int = QSV_C64,
     return gate_pass[:n_g], gate_order[:n_g], pass_kind[:p], pass_qubits[:p]
 
 
+def plan_program_stats(circ: Circuit, n: int, prec: int = QSV_C64,
+                       opts: Optional[qsv_fuse_opts] = None) -> dict:
+    """Host-only dry run of the device program: pass, tile-pass, segment,
+    op and phase-block counts."""
+    out = np.zeros(6, np.uint64)
+    st = circ.struct()
+    _check(_lib.qsv_plan_program_stats(
+        C.byref(st), n, prec, C.byref(opts) if opts is not None else None,
+        _ptr(out, C.c_uint64), 6))
+    keys = ("passes", "tile_passes", "segments", "tile_ops", "phase_blocks",
+            "block_gates")
+    return {k: int(v) for k, v in zip(keys, out)}
+
+
 def debug_emulate_tiled(circ: Circuit, n: int, state: np.ndarray,
                         opts: Optional[qsv_fuse_opts] = None) -> np.ndarray:
     """Host emulation of the tiled device program (testing aid)."""
@@ -415,10 +431,11 @@ class State:
                                     C.byref(opts) if opts is not None else None))
 
     def plan_stats(self) -> dict:
-        out = np.zeros(8, np.uint64)
-        _check(_lib.qsv_last_plan_stats(self._h, _ptr(out, C.c_uint64), 8))
+        out = np.zeros(11, np.uint64)
+        _check(_lib.qsv_last_plan_stats(self._h, _ptr(out, C.c_uint64), 11))
         keys = ("passes", "gates", "alg_bytes", "tile_passes", "plain_passes",
-                "fused_passes", "segments", "plan_ns")
+                "fused_passes", "segments", "plan_ns", "tile_ops",
+                "phase_blocks", "block_gates")
         return {k: int(v) for k, v in zip(keys, out)}
 
     def set_profiling(self, enable: bool):

@@ -10,6 +10,7 @@ import pytest
 import oracle
 from circuits import Gate, layered_circuit, qft_style_circuit, random_state
 from paper_2502_11385_amd import qsv
+from diag_programs import diagonal_heavy, is_diagonal
 
 
 def _mixed(n, count, seed):
@@ -201,3 +202,61 @@ def test_emulated_random_programs(seed, n, L):
     got = qsv.debug_emulate_tiled(circ, n, v,
                                   qsv.fuse_opts(tile_log2=L, low_qubits=2))
     assert np.max(np.abs(got - want)) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# phase blocks: runs of diagonal gates applied as one phase polynomial
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("n,opts", [
+    (10, dict(tile_log2=8, low_qubits=2)),
+    (11, dict(tile_log2=9, low_qubits=3, reg_log2=5)),
+    (12, dict(tile_log2=10, low_qubits=2, reg_log2=3)),
+    (9, dict(tile_log2=9)),
+])
+def test_phase_blocks_emulated(seed, n, opts):
+    """Diagonal-heavy random programs: the tile program (with phase blocks)
+    executed on the host equals the gates applied one by one by the oracle;
+    most diagonal gates land in phase blocks."""
+    gl = diagonal_heavy(n, 240, 100 + seed)
+    circ = qsv.Circuit()
+    want = random_state(n, seed)
+    v = want.copy()
+    for u, t, c in gl:
+        circ.add(t, u, c)
+        want = oracle.apply_gate(want, n, np.asarray(u, complex), t, c)
+    o = qsv.fuse_opts(**opts)
+    got = qsv.debug_emulate_tiled(circ, n, v, o)
+    assert np.max(np.abs(got - want)) < 1e-12
+    st = qsv.plan_program_stats(circ, n, qsv.QSV_C64, o)
+    n_diag = sum(1 for u, _, _ in gl if is_diagonal(u))
+    assert st["phase_blocks"] > 0
+    assert st["block_gates"] > n_diag // 2
+
+
+def test_phase_blocks_qft_ladder():
+    """The QFT ladder's controlled phases go into phase blocks, and the
+    program still reproduces the oracle."""
+    n = 12
+    _, gates = qft_style_circuit(n, 7, tail_layers=1)
+    circ = qsv.Circuit.from_gates(gates)
+    v = random_state(n, 2)
+    want = oracle.simulate(n, gates, init=v)
+    for opts in (dict(tile_log2=8, low_qubits=3), dict(tile_log2=10)):
+        o = qsv.fuse_opts(**opts)
+        got = qsv.debug_emulate_tiled(circ, n, v, o)
+        assert np.max(np.abs(got - want)) < 1e-12
+        st = qsv.plan_program_stats(circ, n, qsv.QSV_C64, o)
+        n_cp = sum(1 for g in gates if g.name == "cp")
+        assert st["block_gates"] >= n_cp // 2
+
+
+def test_program_stats_match_describe():
+    gates = layered_circuit(14, 6, 3)
+    circ = qsv.Circuit.from_gates(gates)
+    o = qsv.fuse_opts(strategy=qsv.PLAN_TILED, tile_log2=10)
+    st = qsv.plan_program_stats(circ, 14, qsv.QSV_C64, o)
+    _, _, kinds, _ = qsv.plan_describe(circ, 14, qsv.QSV_C64, o)
+    assert st["passes"] == len(kinds)
+    assert st["tile_passes"] == int(np.sum(kinds == 2))
+    assert st["segments"] >= st["tile_passes"]
