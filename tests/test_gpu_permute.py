@@ -96,3 +96,45 @@ def test_30q_gate_relabelling_and_round_trip():
     assert torch.equal(before, tb)
     a.free()
     b.free()
+
+
+@pytest.mark.parametrize("n,prec", [(34, C64), (33, C128), (32, C128)])
+def test_relabelling_at_full_width(n, prec):
+    """The widest states (relabelling keeps a second state-sized buffer, so
+    2 x 128 GiB at 34 qubits complex64 and 33 qubits complex128): a sum of 8
+    basis states lands exactly where the permutation sends each index, and
+    the inverse permutation brings it back (checked through the exact top-k
+    of the device state)."""
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(n)
+    x = int(rng.integers(0, 1 << n, dtype=np.uint64))
+    hq = [0, 17, n - 1]
+    perm = rng.permutation(n).tolist()
+    inv = [0] * n
+    for q in range(n):
+        inv[perm[q]] = q
+
+    def relabel(i, pm):
+        return sum(((i >> q) & 1) << pm[q] for q in range(n))
+
+    base = x & ~sum(1 << q for q in hq)
+    start = sorted(base | sum(((v >> j) & 1) << q for j, q in enumerate(hq))
+                   for v in range(8))
+    s = qsv.State(n, prec)
+    try:
+        s.init_basis(x)
+        h = qsv.gate_matrix("h")
+        for q in hq:
+            s.apply_gate([q], h)
+        s.permute_qubits(perm)
+        idx, p = s.top_k(8)
+        assert sorted(int(i) for i in idx) == sorted(relabel(i, perm)
+                                                     for i in start)
+        assert np.allclose(p, 0.125, atol=1e-6)
+        s.permute_qubits(inv)
+        idx, p = s.top_k(8)
+        assert sorted(int(i) for i in idx) == start
+        assert np.allclose(p, 0.125, atol=1e-6)
+    finally:
+        s.free()
+        torch.cuda.empty_cache()
