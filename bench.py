@@ -35,6 +35,11 @@ TILE_SRC = [os.path.join(ROOT, "paper_2502_11385_amd", "csrc", f)
                       "program.h", "planner.cpp")]
 
 
+def _note(msg: str) -> None:
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _src_hash(paths) -> str:
     h = hashlib.sha256()
     for p in paths:
@@ -76,17 +81,51 @@ def cpu_baseline_leg(budget_s: float) -> dict:
                        f"{dt:.1f} s; bytes counted as plain per-gate passes")}
 
 
-def run_cpu_baseline(budget_s: float) -> dict:
+def cpu_batch_leg(budget_s: float) -> dict:
+    """The oracle (one thread) on the cut-variant batch, variant by variant
+    in generation order until the budget is spent: prologue, gates and
+    epilogue, then the probability vector; circuits per second."""
+    import numpy as np
+    import oracle
+    from circuits import batch_variants
+    vs = batch_variants(BATCH_COUNT, seed=BATCH_SEED)
+    done = 0
+    t0 = time.perf_counter()
+    for v in vs:
+        gates = (oracle.cut_prologue(v.cut_inputs) + list(v.gates) +
+                 oracle.cut_epilogue(v.cut_outputs))
+        psi = oracle.simulate(v.width, gates)
+        np.abs(psi) ** 2
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"circuits_per_s": done / dt, "cores": 1,
+            "sample": (f"first {done} of {BATCH_COUNT} variants (seed "
+                       f"{BATCH_SEED}), complex128, {dt:.1f} s")}
+
+
+def _cpu_subprocess(flag: str, budget_s: float):
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         env[k] = "1"
     r = subprocess.run([sys.executable, os.path.abspath(__file__),
-                        "--cpu-leg", str(budget_s)], env=env,
+                        flag, str(budget_s)], env=env,
                        capture_output=True, text=True, timeout=600)
     if r.returncode != 0:
+        return None, r.stderr[-300:]
+    return json.loads(r.stdout.strip().splitlines()[-1]), None
+
+
+def run_cpu_baseline(budget_s: float, batch_budget_s: float) -> dict:
+    res, err = _cpu_subprocess("--cpu-leg", budget_s)
+    if res is None:
         return {"value": None, "unit": "GB/s", "cores": 1, "kind": "oracle",
-                "sample": "failed: " + r.stderr[-300:]}
-    return json.loads(r.stdout.strip().splitlines()[-1])
+                "sample": "failed: " + err}
+    if batch_budget_s > 0:
+        bres, berr = _cpu_subprocess("--cpu-batch-leg", batch_budget_s)
+        res["batch"] = bres if bres is not None else {"failed": berr}
+    return res
 
 
 # --------------------------------------------------------------- batch leg
@@ -324,11 +363,15 @@ def _replay(qsv, reqs, circs, arrivals, serial: bool) -> dict:
     def waiter():
         for i in range(len(reqs)):
             ready.acquire()
-            _, info = srv.wait(tickets[i], copy=False)
+            try:
+                _, info = srv.wait(tickets[i], copy=False)
+            except qsv.QsvError as e:   # the request completed with an error
+                info = {"failed": str(e)}
             srv.release(tickets[i])
             infos[i] = info
 
-    th = threading.Thread(target=waiter)
+    # a daemon, so that an error in the submitting thread ends the process
+    th = threading.Thread(target=waiter, daemon=True)
     th.start()
     t0 = time.perf_counter()
     for i, r in enumerate(reqs):
@@ -344,9 +387,13 @@ def _replay(qsv, reqs, circs, arrivals, serial: bool) -> dict:
     th.join()
     st = srv.stats()
     srv.close()
-    lat = np.array([x["t_done"] - x["t_submit"] for x in infos])
-    span = max(x["t_done"] for x in infos) - min(x["t_submit"] for x in infos)
+    ok = [x for x in infos if "failed" not in x]
+    if not ok:
+        raise RuntimeError("every request failed: " + infos[0]["failed"])
+    lat = np.array([x["t_done"] - x["t_submit"] for x in ok])
+    span = max(x["t_done"] for x in ok) - min(x["t_submit"] for x in ok)
     return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "failed": len(infos) - len(ok),
             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
             "circuits_per_s": round(len(reqs) / span, 2),
             "batch_launches": st["batch_launches"],
@@ -371,6 +418,7 @@ def serve_leg(qsv, n: int) -> dict:
     _replay(qsv, reqs[:100], circs[:100], [0.0] * 100, True)
     mu = _replay(qsv, reqs[100:], circs[100:], [0.0] * n, True)[
         "circuits_per_s"]
+    _note(f"serve: serial service rate {mu:.1f} circuits/s")
     base = np.array([r.arrival_s for r in reqs[100:]])
     base = base - base[0]
     out = {"workload": (f"{n} requests, widths 8..28, depths 10..100, "
@@ -381,10 +429,12 @@ def serve_leg(qsv, n: int) -> dict:
         lam = f * mu
         arr = base / lam            # the unit-rate trace scaled to lam
         key = f"lambda_{f}x"
-        out[key] = {"rate_per_s": round(lam, 2),
-                    "serial": _replay(qsv, reqs[100:], circs[100:], arr, True),
-                    "continuous": _replay(qsv, reqs[100:], circs[100:], arr,
-                                          False)}
+        ser = _replay(qsv, reqs[100:], circs[100:], arr, True)
+        _note(f"serve: {f}x serial done")
+        con = _replay(qsv, reqs[100:], circs[100:], arr, False)
+        _note(f"serve: {f}x continuous done")
+        out[key] = {"rate_per_s": round(lam, 2), "serial": ser,
+                    "continuous": con}
     return out
 
 
@@ -405,6 +455,9 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--cpu-batch-leg", type=float, default=None,
+                    help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-batch-budget", type=float, default=8.0)
     ap.add_argument("--cpu-leg", type=float, default=None,
                     help=argparse.SUPPRESS)
     ap.add_argument("--no-batch", action="store_true",
@@ -425,6 +478,9 @@ def main() -> int:
 
     if a.cpu_leg is not None:
         print(json.dumps(cpu_baseline_leg(a.cpu_leg)))
+        return 0
+    if a.cpu_batch_leg is not None:
+        print(json.dumps(cpu_batch_leg(a.cpu_batch_leg)))
         return 0
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); "
@@ -466,6 +522,7 @@ def main() -> int:
         smp = state.sample(SHOTS, SAMPLE_SEED)  # waits for the stream
         return marg, smp
 
+    _note(f"headline: {a.warmup} warm-up and {a.steps} timed steps")
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
@@ -597,18 +654,29 @@ def main() -> int:
     del probs
     torch.cuda.empty_cache()
     if not a.no_plans:
+        _note("plans leg")
         out["plans"] = plans_leg(qsv, torch, np, circ, n)
     if not a.no_wide:
+        _note("wide leg")
         out["wide"] = wide_leg(qsv, torch, np)
     if not a.no_cut:
+        _note("cut leg")
         out["cut"] = cut_leg(qsv, torch, np, max(1, a.steps))
     if not a.no_batch:
+        _note("batch leg")
         out["batch"] = batch_leg(qsv, torch, np, max(1, a.steps),
                                  not a.no_per_circuit)
     if not a.no_serve:
+        _note("serve leg")
         out["serve"] = serve_leg(qsv, a.serve_n)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = run_cpu_baseline(a.cpu_budget)
+        _note("cpu baseline (oracle)")
+        out["cpu_baseline"] = run_cpu_baseline(
+            a.cpu_budget, 0.0 if a.no_batch else a.cpu_batch_budget)
+        cb = out["cpu_baseline"].get("batch") or {}
+        if "batch" in out and cb.get("circuits_per_s"):
+            out["batch"]["speedup_vs_oracle_cpu"] = round(
+                out["batch"]["circuits_per_s"] / cb["circuits_per_s"], 1)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -412,7 +412,10 @@ typedef struct qsv_server_s* qsv_server;
 qsv_status qsv_server_create(const qsv_server_opts* opts, qsv_server* out);
 
 /* Validate and enqueue a request (inputs are copied); returns its ticket.
- * QSV_ERR_BUDGET if the request alone exceeds the budget. */
+ * QSV_ERR_BUDGET if the request alone exceeds the budget.  The pinned host
+ * buffer for its result is taken when the request is admitted to the
+ * device; if that allocation fails the request completes with
+ * QSV_ERR_OUT_OF_MEMORY (reported by qsv_server_wait). */
 qsv_status qsv_server_submit(qsv_server s, const qsv_request* req,
                              uint64_t* ticket);
 

@@ -421,6 +421,19 @@ void scheduler(qsv_server s) {
         const bool opens = !r->batched || in_batch[r->prec] == 0 ||
                            in_batch[r->prec] >= s->o.max_batch;
         if (opens && groups + 1 > slots) break;
+        // the pinned result buffer is taken at admission, so that a long
+        // queue holds no pinned memory; the client's release returns it
+        r->host = s->hpool.get(std::max<size_t>(r->host_bytes, 8));
+        if (!r->host) {
+          s->pending.pop_front();
+          r->status = QSV_ERR_OUT_OF_MEMORY;
+          r->err = "pinned result buffer allocation failed";
+          r->t_admit = r->t_done = now_s();
+          r->done = true;
+          s->completed++;
+          s->cv_done.notify_all();
+          continue;
+        }
         if (opens) {
           ++groups;
           if (r->batched) in_batch[r->prec] = 0;
@@ -580,11 +593,6 @@ qsv_status qsv_server_submit(qsv_server s, const qsv_request* rq,
     s->rejected++;
     delete r;
     return set_error(QSV_ERR_BUDGET, "request needs more HBM than the budget");
-  }
-  r->host = s->hpool.get(std::max<size_t>(r->host_bytes, 8));
-  if (!r->host) {
-    delete r;
-    return set_error(QSV_ERR_OUT_OF_MEMORY, "pinned result buffer allocation failed");
   }
   r->ticket = s->next_ticket++;
   r->t_submit = now_s();

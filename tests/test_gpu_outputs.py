@@ -120,3 +120,57 @@ def test_pauli_mask_beyond_n_rejected():
         s.expectation([{7: "Z"}])
     assert e.value.status == qsv.QSV_ERR_INVALID_ARG
     s.free()
+
+
+@pytest.mark.parametrize("n,prec", [(34, C64), (33, C128)])
+def test_outputs_at_full_width(n, prec):
+    """Every output of the widest states on a state with a closed form: a
+    basis state x with H on three qubits (8 outcomes of probability 1/8).
+    Norm, FP32 probability vector (sampled entries), Pauli expectations
+    (<Z_q> = (-1)^{x_q} off the H qubits, <X_q> = (-1)^{x_q} and <Z_q> = 0
+    on them),
+    top-8, marginal of the top 10 qubits and shots."""
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(n + 100)
+    x = int(rng.integers(0, 1 << n, dtype=np.uint64))
+    hq = [1, 20, n - 1]
+    zq = 7
+    base = x & ~sum(1 << q for q in hq)
+    support = sorted(base | sum(((v >> j) & 1) << q for j, q in enumerate(hq))
+                     for v in range(8))
+    tol = 1e-6 if prec == C64 else 1e-12
+    s = qsv.State(n, prec)
+    try:
+        s.init_basis(x)
+        h = qsv.gate_matrix("h")
+        for q in hq:
+            s.apply_gate([q], h)
+        assert abs(s.norm() - 1.0) < tol
+        ev = s.expectation([{zq: "Z"}, {hq[1]: "X"}, {hq[1]: "Z"},
+                            {hq[0]: "X", hq[2]: "X", zq: "Z"}])
+        def sg(q):
+            return -1.0 if (x >> q) & 1 else 1.0
+        # H|b> has <X> = (-1)^b and <Z> = 0; an untouched qubit <Z> = (-1)^b
+        assert np.allclose(ev, [sg(zq), sg(hq[1]), 0.0,
+                                sg(hq[0]) * sg(hq[2]) * sg(zq)], atol=tol)
+        idx, p = s.top_k(8)
+        assert sorted(int(i) for i in idx) == support
+        assert np.allclose(p, 0.125, atol=tol)
+        marg = s.marginal(list(range(n - 10, n)))
+        want = np.zeros(1024)
+        for i in support:
+            want[i >> (n - 10)] += 0.125
+        assert np.max(np.abs(marg - want)) < tol
+        shots = s.sample(4096, 77)
+        assert set(int(v) for v in shots) <= set(support)
+        probs = s.probabilities(fp64=False)
+        pick = torch.tensor(support + [support[0] ^ (1 << zq), 0, (1 << n) - 1],
+                            device="cuda")
+        got = probs[pick].cpu().numpy().astype(np.float64)
+        want = [0.125] * 8 + [0.0] + [0.125 if i in support else 0.0
+                                      for i in (0, (1 << n) - 1)]
+        assert np.allclose(got, want, atol=1e-7)
+        del probs
+    finally:
+        s.free()
+        torch.cuda.empty_cache()
