@@ -36,15 +36,9 @@ enum : int32_t {
 //  lctrl: controls inside the tile as a mask of tile-local bits.
 //  gctrl: controls outside the tile as a mask of global qubits.
 struct alignas(16) TileOp {
+  // header (the first 48 bytes, read by the kernels in one batch)
   int32_t kind;
   int32_t reg;
-  int32_t dk;
-  int32_t dbit0;
-  int32_t dbit1;
-  uint32_t lctrl;
-  uint64_t gctrl;
-  double m[8];
-  float mf[8];  // m rounded to FP32 (complex64 states)
   // kOpDense1 only: the matrix may depend on one more qubit ("mux"):
   // kMuxNone, a tile-local bit (>= 0) or an outer qubit q as -1 - q.  The
   // op applies m where that bit is 0 and m2 where it is 1.
@@ -53,10 +47,17 @@ struct alignas(16) TileOp {
   // holds it in the op's segment, or -1 when a thread bit holds it (then the
   // matrix is fixed per thread).  -1 for every other op.
   int32_t mux_reg;
-  double m2[8];
-  float mf2[8];
+  uint32_t lctrl;
+  int32_t dk;
+  int32_t dbit0;
+  int32_t dbit1;
+  uint64_t gctrl;
   int32_t blob;  // kOpPhaseBlock only
   int32_t pad_;
+  float mf[8];   // m rounded to FP32 (complex64 states)
+  float mf2[8];
+  double m[8];
+  double m2[8];
 };
 
 constexpr int32_t kMuxNone = -1000;
@@ -73,10 +74,10 @@ constexpr int kMaxRegBits = 5;
 
 struct alignas(16) PhaseTerm {
   uint64_t gmask;    // outer qubits that must be 1
-  uint64_t turns;    // angle / (2 pi) * 2^64, modulo 2^64
   uint32_t tmask;    // thread bits (tile-local) that must be 1
   uint32_t turns32;  // turns rounded to 32 bits (complex64)
-  uint32_t pad[2];
+  uint64_t turns;    // angle / (2 pi) * 2^64, modulo 2^64
+  uint64_t pad;
 };
 
 // Accumulator 0 holds the terms without a register bit; accumulator 1 + r

@@ -294,22 +294,36 @@ __device__ __forceinline__ void phase_block(typename CxT<T>::type* a,
   constexpr int R = 1 << RB;
   const PhaseTerm* t = reinterpret_cast<const PhaseTerm*>(pb + 1);
   U acc[RB + 1];
+  // A term's first 16 bytes (outer mask, thread mask, 32-bit turns) are
+  // read as one vector, so that each term costs one scalar load round trip.
+  auto head = [](const PhaseTerm* p, uint64_t* gm, uint32_t* tm, U* w) {
+    const uint4 h = *reinterpret_cast<const uint4*>(p);
+    *gm = uint64_t(h.x) | (uint64_t(h.y) << 32);
+    *tm = h.z;
+    if constexpr (sizeof(T) == 4) *w = U(h.w);
+    else *w = U(p->turns);
+  };
 #pragma unroll
   for (int k = 0; k <= RB; ++k) {
     U au = 0;
     const int nu = pb->n_uni[k];
+#pragma unroll 4
     for (int i = 0; i < nu; ++i, ++t) {
-      const uint64_t gm = t->gmask;
-      const U w = sizeof(T) == 4 ? U(t->turns32) : U(t->turns);
+      uint64_t gm;
+      uint32_t tm;
+      U w;
+      head(t, &gm, &tm, &w);
       au += (base & gm) == gm ? w : U(0);
     }
     U av = 0;
     const int nv = pb->n_thr[k];
+#pragma unroll 4
     for (int i = 0; i < nv; ++i, ++t) {
-      const uint64_t gm = t->gmask;
-      const uint32_t tm = t->tmask;
-      const U w = sizeof(T) == 4 ? U(t->turns32) : U(t->turns);
-      const bool on = ((base & gm) == gm) && ((rt & tm) == tm);
+      uint64_t gm;
+      uint32_t tm;
+      U w;
+      head(t, &gm, &tm, &w);
+      const bool on = ((base & gm) == gm) & ((rt & tm) == tm);
       av += on ? w : U(0);
     }
     acc[k] = au + av;
@@ -384,42 +398,54 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
 
     for (int o = sp[s].op_begin; o < sp[s].op_end; ++o) {
       const TileOp* op = ops + o;
-      const uint64_t gctrl = op->gctrl;
-      if ((base & gctrl) != gctrl) continue;  // an outer control bit is 0
+      // Read the header and both matrices before any branch, so that the
+      // scalar loads issue together and the op waits for them once (a
+      // variant that prefetched the next op's fields during this op was
+      // slower: the copies and the register pressure cost more than the
+      // latency it hid).
       const int kind = op->kind;
+      const int oreg = op->reg;
+      const int mux = op->mux;
+      const int mreg = op->mux_reg;
       const uint32_t lctrl = op->lctrl;
+      const uint64_t gctrl = op->gctrl;
+      T m0[8], m1[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        if constexpr (sizeof(T) == 4) {
+          m0[e] = op->mf[e];
+          m1[e] = op->mf2[e];
+        } else {
+          m0[e] = op->m[e];
+          m1[e] = op->m2[e];
+        }
+      }
+      if ((base & gctrl) != gctrl) continue;  // an outer control bit is 0
       if (kind == kOpDense1) {
-        const int mux = op->mux;
         // an outer mux qubit is fixed per tile: pick the matrix once
         const bool second =
             mux != kMuxNone && mux < 0 && ((base >> ((-1 - mux) & 63)) & 1);
         T m[8], m2[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          if constexpr (sizeof(T) == 4) {
-            m[e] = second ? op->mf2[e] : op->mf[e];
-            m2[e] = op->mf2[e];
-          } else {
-            m[e] = second ? op->m2[e] : op->m[e];
-            m2[e] = op->m2[e];
-          }
+          m[e] = second ? m1[e] : m0[e];
+          m2[e] = m1[e];
         }
-        const int mreg = op->mux_reg;
         if (mux >= 0 && lctrl == 0 && mreg >= 0) {
           // mux bit in a register: the pairs' matrices are fixed
-          dense1_muxreg_dispatch<R>(op->reg, mreg, a, m, m2);
+          dense1_muxreg_dispatch<R>(oreg, mreg, a, m, m2);
         } else if (mux >= 0 && lctrl == 0) {
           // mux bit in the thread index: one matrix per thread
           const bool sel = ((rt >> mux) & 1u) != 0;
 #pragma unroll
           for (int e = 0; e < 8; ++e) m[e] = sel ? m2[e] : m[e];
-          dense1_dispatch<R, false>(op->reg, a, m, rt, lr, lctrl);
+          dense1_dispatch<R, false>(oreg, a, m, rt, lr, lctrl);
         } else if (mux >= 0) {
-          dense1_mux_dispatch<R, true>(op->reg, a, m, m2, rt, lr, lctrl, mux);
+          dense1_mux_dispatch<R, true>(oreg, a, m, m2, rt, lr, lctrl, mux);
         } else if (lctrl) {
-          dense1_dispatch<R, true>(op->reg, a, m, rt, lr, lctrl);
+          dense1_dispatch<R, true>(oreg, a, m, rt, lr, lctrl);
         } else {
-          dense1_dispatch<R, false>(op->reg, a, m, rt, lr, lctrl);
+          dense1_dispatch<R, false>(oreg, a, m, rt, lr, lctrl);
         }
       } else if (kind == kOpPhaseBlock) {
         phase_block<T, RB>(
@@ -429,13 +455,8 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
             rt, base);
       } else if (kind == kOpPhase) {
         C ph;
-        if constexpr (sizeof(T) == 4) {
-          ph.x = op->mf[0];
-          ph.y = op->mf[1];
-        } else {
-          ph.x = op->m[0];
-          ph.y = op->m[1];
-        }
+        ph.x = m0[0];
+        ph.y = m0[1];
         // the index's thread and register parts have disjoint bits
         const uint32_t tm = rt & lctrl;
 #pragma unroll
@@ -454,13 +475,8 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
         C t[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          if constexpr (sizeof(T) == 4) {
-            t[e].x = op->mf[2 * e];
-            t[e].y = op->mf[2 * e + 1];
-          } else {
-            t[e].x = op->m[2 * e];
-            t[e].y = op->m[2 * e + 1];
-          }
+          t[e].x = m0[2 * e];
+          t[e].y = m0[2 * e + 1];
         }
         // thread parts of the two index bits, once per op
         const uint32_t t0 = d0 >= 0 ? (rt >> (d0 & 31)) & 1u : g0;

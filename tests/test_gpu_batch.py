@@ -124,3 +124,25 @@ def test_empty_body_variant():
     b.launch(out)
     torch.cuda.synchronize()
     _check(out, b.offsets, vs, C128)
+
+
+@pytest.mark.parametrize("prec", [C64, C128])
+def test_batch_extreme_widths(prec):
+    """The narrowest and widest variants a batch accepts (reg_log2 + 2 = 6
+    and QSV_BATCH_MAX_WIDTH = 24) ragged in one batch, with a mid-width one
+    between them, against the oracle."""
+    vs = (batch_variants(count=2, seed=21, wmin=6, wmax=6, dmin=3, dmax=6) +
+          batch_variants(count=1, seed=22, wmin=24, wmax=24, dmin=2, dmax=2) +
+          batch_variants(count=1, seed=23, wmin=13, wmax=13, dmin=4, dmax=4))
+    b = qsv.Batch(vs, prec=prec, out_fp64=(prec == C128))
+    out = b.output()
+    b.launch(out)
+    torch.cuda.synchronize()
+    _check(out, b.offsets, vs, prec)
+    b.free()
+    with pytest.raises(qsv.QsvError):
+        qsv.Batch(batch_variants(count=1, seed=24, wmin=25, wmax=25, dmin=1,
+                                 dmax=1), prec=prec)
+    with pytest.raises(qsv.QsvError):
+        qsv.Batch(batch_variants(count=1, seed=25, wmin=5, wmax=5, dmin=1,
+                                 dmax=1), prec=prec)
