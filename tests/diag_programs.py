@@ -1,5 +1,5 @@
-"""Seeded diagonal-heavy gate programs for the phase-block tests (inputs
-only: gate matrices as NumPy arrays with their target and control lists)."""
+"""Seeded random gate programs for the parity tests (inputs only: gate
+matrices as NumPy arrays with their target and control lists)."""
 import math
 
 import numpy as np
@@ -53,3 +53,55 @@ def diagonal_heavy(n, count, seed, non_unitary=True):
 def is_diagonal(u):
     u = np.asarray(u)
     return np.count_nonzero(u - np.diag(np.diag(u))) == 0
+
+
+def _unitary(d, rng):
+    """A Haar-random d x d unitary (QR of a complex Gaussian matrix)."""
+    z = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def random_gates(n, count, rng):
+    """Gates of every form the library accepts: dense 1..3-target unitaries
+    with 0..2 controls, unitary diagonals, masked phases and diagonals that
+    are not phases.  Returns [(matrix, targets, controls)]."""
+    out = []
+    for _ in range(count):
+        kind = int(rng.integers(0, 9))
+        k = 1 if kind < 4 else int(rng.integers(1, 4))
+        c = int(rng.integers(0, 3))
+        c = min(c, n - k)
+        qs = [int(v) for v in rng.choice(n, k + c, replace=False)]
+        t, ctl = qs[:k], qs[k:]
+        if kind <= 3:        # dense 1-qubit, 0..2 controls
+            u = _unitary(2, rng)
+        elif kind <= 5:      # dense k-qubit
+            u = _unitary(1 << k, rng)
+        elif kind == 6:      # unitary diagonal
+            u = np.diag(np.exp(1j * rng.uniform(-7, 7, 1 << k)))
+        elif kind == 7:      # masked phase
+            d = np.ones(1 << k, complex)
+            d[-1] = np.exp(1j * rng.uniform(-7, 7))
+            u = np.diag(d)
+        else:                # a diagonal that is not a phase
+            u = np.diag(rng.uniform(0.5, 1.5, 1 << k) *
+                        np.exp(1j * rng.uniform(-3, 3, 1 << k)))
+        out.append((u, t, ctl))
+    return out
+
+
+def random_opts(rng, c128):
+    """Plan options within the documented ranges (reg_log2 <= 4 for
+    complex128, tile_log2 - reg_log2 <= 9)."""
+    strategy = int(rng.integers(1, 4))          # plain, fused, tiled
+    L = int(rng.integers(8, 14))
+    rb = int(rng.integers(3, 5 if c128 else 6))
+    rb = max(rb, L - 9)
+    if c128:
+        rb = min(rb, 4)
+        L = min(L, rb + 9)
+    low = int(rng.integers(0, min(L, 7)))
+    kmax = int(rng.integers(1, 6))
+    return dict(strategy=strategy, tile_log2=L, reg_log2=rb,
+                low_qubits=low, k_max=kmax)

@@ -260,3 +260,25 @@ def test_program_stats_match_describe():
     assert st["passes"] == len(kinds)
     assert st["tile_passes"] == int(np.sum(kinds == 2))
     assert st["segments"] >= st["tile_passes"]
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_emulated_random_programs_random_options(seed):
+    """Random gate lists of every accepted form under random tile options
+    (tile size, register bits, low qubits), tile program run on the host,
+    against the oracle applying every gate in order."""
+    from diag_programs import random_gates, random_opts
+    rng = np.random.default_rng(7000 + seed)
+    n = int(rng.integers(6, 15))
+    gl = random_gates(n, int(rng.integers(20, 160)), rng)
+    o = random_opts(rng, False)
+    o["strategy"] = qsv.PLAN_TILED
+    circ = qsv.Circuit()
+    want = random_state(n, seed)
+    v = want.copy()
+    for u, t, c in gl:
+        circ.add(t, u, c)
+        want = oracle.apply_gate(want, n, np.asarray(u, complex), t, c)
+    got = qsv.debug_emulate_tiled(circ, n, v, qsv.fuse_opts(**o))
+    scale = max(1.0, float(np.max(np.abs(want))))
+    assert np.max(np.abs(got - want)) / scale < 1e-12, o
