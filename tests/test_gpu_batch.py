@@ -146,3 +146,27 @@ def test_batch_extreme_widths(prec):
     with pytest.raises(qsv.QsvError):
         qsv.Batch(batch_variants(count=1, seed=25, wmin=5, wmax=5, dmin=1,
                                  dmax=1), prec=prec)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_batch_random_options(seed):
+    """Seeded random batches (widths reg_log2 + 2..16, depths 1..20) under
+    random tile
+    and register sizes, precision, output precision and grid, against the
+    oracle."""
+    rng = np.random.default_rng(500 + seed)
+    prec = C64 if seed % 2 == 0 else C128
+    rb = 4 if prec == C128 else int(rng.integers(4, 6))
+    L = int(rng.integers(8, min(12, rb + 8) + 1))
+    grid = int(rng.choice([0, 1, 7, 64, 300]))
+    out64 = bool(prec == C128 or rng.integers(0, 2))
+    vs = batch_variants(count=int(rng.integers(1, 14)), seed=600 + seed,
+                        wmin=rb + 2, wmax=16, dmin=1, dmax=20)
+    b = qsv.Batch(vs, prec=prec, out_fp64=out64, tile_log2=L, reg_log2=rb,
+                  grid=grid)
+    out = b.output()
+    b.launch(out)
+    b.launch(out)            # a second launch over the same buffers
+    torch.cuda.synchronize()
+    _check(out, b.offsets, vs, prec)
+    b.free()
