@@ -105,6 +105,34 @@ def cpu_batch_leg(budget_s: float) -> dict:
                        f"{BATCH_SEED}), complex128, {dt:.1f} s")}
 
 
+def cpu_configs_leg(budget_s: float) -> dict:
+    """The oracle (one thread) on the other configurations' CPU-sized
+    instances: the 12-qubit layered circuit and GHZ-12 with their
+    probability vectors, and the 20-qubit instance of the QFT-style circuit
+    (seed 34) with its top-10 marginal; seconds per circuit."""
+    import numpy as np
+    import oracle
+    from circuits import ghz_circuit, layered_circuit, qft_style_circuit
+    out = {"cores": 1}
+    for name, n, make in (("layered12", 12, lambda: (0, layered_circuit(12, 20, 12))),
+                          ("ghz12", 12, lambda: (0, ghz_circuit(12))),
+                          ("qft_style20", 20, lambda: qft_style_circuit(20, 34))):
+        x, gates = make()
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            psi = oracle.simulate(n, gates, init=x)
+            p = np.abs(psi) ** 2
+            if n == 20:
+                p.reshape(1 << 10, 1 << 10).sum(axis=1)
+            reps += 1
+            if time.perf_counter() - t0 > budget_s / 3 or reps >= 50:
+                break
+        out[name] = {"s_per_circuit": (time.perf_counter() - t0) / reps,
+                     "gates": len(gates), "reps": reps}
+    return out
+
+
 def _cpu_subprocess(flag: str, budget_s: float):
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
@@ -125,6 +153,8 @@ def run_cpu_baseline(budget_s: float, batch_budget_s: float) -> dict:
     if batch_budget_s > 0:
         bres, berr = _cpu_subprocess("--cpu-batch-leg", batch_budget_s)
         res["batch"] = bres if bres is not None else {"failed": berr}
+    cres, cerr = _cpu_subprocess("--cpu-configs-leg", 6.0)
+    res["configs"] = cres if cres is not None else {"failed": cerr}
     return res
 
 
@@ -137,6 +167,44 @@ EPILOGUE = {"I": [], "X": ["h"], "Y": ["sdg", "h"]}
 
 CUT_WIDTHS, CUT_DEPTH, CUT_SEED = (10, 12, 10), 20, 30
 PLAIN_C128_SAMPLE = 256
+
+
+def small_leg(qsv, torch, np, reps: int = 200) -> dict:
+    """The 12-qubit circuits (layered depth 20, seed 12; GHZ-12), each
+    circuit a full call sequence (init, planned passes, FP64 probability
+    vector into a device buffer) on one stream, repeated; microseconds per
+    circuit from the wall clock around `reps` back-to-back circuits."""
+    from circuits import ghz_circuit, layered_circuit
+    n = 12
+    res = {"workload": ("12-qubit layered random circuit (depth 20, 240 U3 + "
+                        "110 CZ, seed 12) and GHZ-12, init + planned passes "
+                        "+ 4096-entry FP64 probabilities per circuit")}
+    probs = torch.empty(1 << n, dtype=torch.float64, device="cuda")
+    for cname, gates in (("layered12", layered_circuit(n, 20, 12)),
+                         ("ghz12", ghz_circuit(n))):
+        circ = qsv.Circuit.from_gates(gates)
+        for pname, prec in (("c64", qsv.QSV_C64), ("c128", qsv.QSV_C128)):
+            s = qsv.State(n, prec, stream=torch.cuda.current_stream())
+            for _ in range(5):
+                s.init_basis(0)
+                s.apply_fused(circ)
+                s.probabilities_into(probs.data_ptr(), True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                s.init_basis(0)
+                s.apply_fused(circ)
+                s.probabilities_into(probs.data_ptr(), True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = s.plan_stats()
+            res[f"{cname}_{pname}"] = {
+                "us_per_circuit": round(dt / reps * 1e6, 1),
+                "passes": st["passes"],
+                "plan_us": round(st["plan_ns"] / 1e3, 1)}
+            s.free()
+    del probs
+    return res
 
 
 def cut_leg(qsv, torch, np, steps: int) -> dict:
@@ -458,6 +526,10 @@ def main() -> int:
     ap.add_argument("--cpu-batch-leg", type=float, default=None,
                     help=argparse.SUPPRESS)
     ap.add_argument("--cpu-batch-budget", type=float, default=8.0)
+    ap.add_argument("--cpu-configs-leg", type=float, default=None,
+                    help=argparse.SUPPRESS)
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 12-qubit circuits leg")
     ap.add_argument("--cpu-leg", type=float, default=None,
                     help=argparse.SUPPRESS)
     ap.add_argument("--no-batch", action="store_true",
@@ -481,6 +553,9 @@ def main() -> int:
         return 0
     if a.cpu_batch_leg is not None:
         print(json.dumps(cpu_batch_leg(a.cpu_batch_leg)))
+        return 0
+    if a.cpu_configs_leg is not None:
+        print(json.dumps(cpu_configs_leg(a.cpu_configs_leg)))
         return 0
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); "
@@ -656,6 +731,9 @@ def main() -> int:
     if not a.no_plans:
         _note("plans leg")
         out["plans"] = plans_leg(qsv, torch, np, circ, n)
+    if not a.no_small:
+        _note("small leg")
+        out["small"] = small_leg(qsv, torch, np)
     if not a.no_wide:
         _note("wide leg")
         out["wide"] = wide_leg(qsv, torch, np)
