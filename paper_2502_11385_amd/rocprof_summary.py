@@ -2,6 +2,9 @@
 
   python -m paper_2502_11385_amd.rocprof_summary stats DB
       per-kernel calls / total / average duration (kernel-trace run)
+  python -m paper_2502_11385_amd.rocprof_summary counters DB --kernel NAME
+      per-counter averages per dispatch (and per wave with SQ_WAVES) of one
+      kernel in a --pmc run
   python -m paper_2502_11385_amd.rocprof_summary traffic FETCH_DB WRITE_DB \
         --kernel tile_kernel --copy-bytes 1073741824 [--json OUT]
       HBM bytes per dispatch of one kernel from FETCH_SIZE and WRITE_SIZE
@@ -86,6 +89,25 @@ def traffic(fetch_db: str, write_db: str, kernel: str, copy_bytes: int):
             "bytes_per_launch": rd + wr}
 
 
+def counters(db: str, kernel: str):
+    """Per counter of a --pmc run: dispatches of `kernel`, average value per
+    dispatch and, when SQ_WAVES was collected, the average per wave."""
+    names = [r[0] for r in _rows(db, "select distinct counter_name from "
+                                      "counters_collection")]
+    per = {c: [v for k, v in counter_per_dispatch(db, c).values()
+               if kernel in k] for c in names}
+    waves = per.get("SQ_WAVES")
+    out = []
+    for c in sorted(names):
+        vals = per[c]
+        if not vals:
+            continue
+        avg = sum(vals) / len(vals)
+        pw = (avg / (sum(waves) / len(waves))) if waves else None
+        out.append((c, len(vals), avg, pw))
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -100,7 +122,17 @@ def main() -> int:
     t.add_argument("--source", default=None, nargs="+",
                    help="kernel source files whose combined hash is recorded")
     t.add_argument("--strategy", default="tiled")
+    k = sub.add_parser("counters")
+    k.add_argument("db")
+    k.add_argument("--kernel", default="tile_kernel")
     a = ap.parse_args()
+    if a.cmd == "counters":
+        print(f"{'counter':24s} {'dispatches':>10} {'avg/dispatch':>16} "
+              f"{'avg/wave':>12}")
+        for c, nd, avg, pw in counters(a.db, a.kernel):
+            pws = f"{pw:12.2f}" if pw is not None else f"{'':>12}"
+            print(f"{c:24s} {nd:10d} {avg:16.1f} {pws}")
+        return 0
     if a.cmd == "stats":
         print(f"{'calls':>6} {'total_ms':>10} {'avg_us':>10}  kernel")
         for n, c, tot, avg in kernel_stats(a.db):
