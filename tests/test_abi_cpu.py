@@ -117,3 +117,26 @@ def test_plan_option_validation():
     with pytest.raises(qsv.QsvError) as e:
         qsv.plan_describe(c, 8, prec=7)
     assert e.value.status == qsv.QSV_ERR_UNSUPPORTED
+
+
+def test_plan_program_stats_validation():
+    c = _circ([([0], [], X), ([1], [0], X)])
+    st = qsv.plan_program_stats(c, 8, qsv.QSV_C64,
+                                qsv.fuse_opts(strategy=qsv.PLAN_TILED))
+    assert st["passes"] == 1 and st["tile_passes"] == 1
+    assert st["tile_ops"] >= 1 and st["phase_blocks"] == 0
+    with pytest.raises(qsv.QsvError) as e:
+        qsv.plan_program_stats(c, 8, prec=7)
+    assert e.value.status == qsv.QSV_ERR_UNSUPPORTED
+    for n in (0, 35):
+        with pytest.raises(qsv.QsvError) as e:
+            qsv.plan_program_stats(c, n)
+        assert e.value.status == qsv.QSV_ERR_INVALID_ARG
+    out = np.zeros(8, np.uint64)
+    import ctypes as C
+    st = c.struct()
+    assert qsv._lib.qsv_plan_program_stats(
+        C.byref(st), 8, qsv.QSV_C64, None,
+        out.ctypes.data_as(C.POINTER(C.c_uint64)), 7) == qsv.QSV_ERR_INVALID_ARG
+    assert qsv._lib.qsv_plan_program_stats(
+        C.byref(st), 8, qsv.QSV_C64, None, None, 1) == qsv.QSV_ERR_INVALID_ARG
