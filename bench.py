@@ -702,6 +702,39 @@ def main() -> int:
              {q: "Z" for q in range(n)}]
     ev = state.expectation(terms)
     t2 = time.perf_counter()
+    # single gates as one plain pass each (k = 1..5 targets spread from
+    # qubit 0 to qubit n-1, and a controlled and a diagonal gate),
+    # HIP-event timed on the state's stream; GB/s = algorithmic bytes / time
+    grng = np.random.default_rng(77)
+
+    def _u(d):
+        z = grng.standard_normal((d, d)) + 1j * grng.standard_normal((d, d))
+        q, r = np.linalg.qr(z)
+        return q * (np.diag(r) / np.abs(np.diag(r)))
+
+    gsp = {1: [n - 1], 2: [0, n - 1], 3: [0, 15, n - 1],
+           4: [0, 7, 22, n - 1], 5: [0, 7, 15, 22, n - 1]}
+    gate_cases = [(f"dense_k{k}", gsp[k], _u(1 << k), [], 2 * state_bytes)
+                  for k in range(1, 6)]
+    gate_cases.append(("controlled_k1", [n - 1], _u(2), [3],
+                       2 * (state_bytes >> 1)))
+    gate_cases.append(("cz", [n - 1], np.diag([1, -1]).astype(complex), [0],
+                       2 * (state_bytes >> 2)))
+    gates_out = {}
+    for gname, tq, gu, gc, gbytes in gate_cases:
+        state.apply_gate(tq, gu, gc)
+        ge0 = torch.cuda.Event(enable_timing=True)
+        ge1 = torch.cuda.Event(enable_timing=True)
+        ge0.record()
+        for _ in range(3):
+            state.apply_gate(tq, gu, gc)
+        ge1.record()
+        torch.cuda.synchronize()
+        gms = ge0.elapsed_time(ge1) / 3
+        gates_out[gname] = {"targets": tq, "controls": gc,
+                            "ms": round(gms, 3),
+                            "GBps": round(gbytes / (gms * 1e-3) / 1e9, 1)}
+    out["gates"] = gates_out
     # relabelling pass (reverse qubit order and back), HIP-event timed
     rev = list(reversed(range(n)))
     state.permute_qubits(rev)                    # allocates its buffer

@@ -96,8 +96,10 @@ qsv_status qsv_init_basis(qsv_state s, uint64_t index);
  * with all target bits 0 and all control bits 1,
  *   a'[i_r] = sum_s U[r][s] a[i_s],  i_r = i | sum_j bit_j(r) << targets[j].
  * This is the per-gate kernel of full-circuit execution (Section III.B,
- * gates u1/u3/CNOT of the cache-blocking example).  Enqueued on the state's
- * stream; the matrix is copied before return. */
+ * gates u1/u3/CNOT of the cache-blocking example).  Gates on 4 or 5 targets
+ * without controls run on the matrix cores (the matrix rounded once to FP32
+ * for complex64 states); all others on the vector units.  Enqueued on the
+ * state's stream; the matrix is copied before return. */
 qsv_status qsv_apply_gate(qsv_state s, const int32_t* targets, int32_t k,
                           const int32_t* controls, int32_t c,
                           const double* matrix);

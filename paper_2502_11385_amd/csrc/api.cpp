@@ -335,6 +335,41 @@ qsv_status qsv_apply_gate(qsv_state s, const int32_t* targets, int32_t k,
   if ((st = select_device(s)) != QSV_OK) return st;
   if (g.diagonal) {
     QSV_HIP(s, launch_diag(s->prec, s->amp, s->n, g, s->stream));
+  } else if (g.k >= 4 && g.c == 0) {
+    // 4-5 targets without controls: the matrix-core block kernel of the
+    // fused plans, with the matrix re-indexed to ascending target order
+    // (block bit j = j-th smallest target) and, for complex64, rounded
+    // once to FP32
+    const int d = 1 << g.k;
+    int32_t q[kMaxK];
+    for (int j = 0; j < g.k; ++j) q[j] = g.t[j];
+    std::sort(q, q + g.k);
+    int pos[kMaxK];
+    for (int i = 0; i < g.k; ++i)
+      for (int j = 0; j < g.k; ++j)
+        if (q[j] == g.t[i]) pos[i] = j;
+    auto perm = [&](int r) {
+      int v = 0;
+      for (int i = 0; i < g.k; ++i) v |= ((r >> i) & 1) << pos[i];
+      return v;
+    };
+    std::vector<double> mp(size_t(2) * d * d);
+    for (int r = 0; r < d; ++r)
+      for (int c2 = 0; c2 < d; ++c2) {
+        const size_t src = size_t(2) * (r * d + c2);
+        const size_t dst = size_t(2) * (perm(r) * d + perm(c2));
+        mp[dst] = g.m[src];
+        mp[dst + 1] = g.m[src + 1];
+      }
+    if (s->prec == QSV_C64) {
+      std::vector<float> mf(mp.begin(), mp.end());
+      if ((st = upload(s, mf.data(), mf.size() * sizeof(float))) != QSV_OK)
+        return st;
+    } else if ((st = upload(s, mp.data(), mp.size() * sizeof(double))) != QSV_OK) {
+      return st;
+    }
+    QSV_HIP(s, launch_fused_apply(s->prec, s->amp, s->n, g.k, q, s->prog_dev,
+                                  s->stream));
   } else if (g.k <= 2) {
     QSV_HIP(s, launch_dense(s->prec, s->amp, s->n, g, nullptr, s->stream));
   } else {

@@ -106,6 +106,29 @@ def test_dense_k_targets_with_controls(prec, k, c):
 
 
 @pytest.mark.parametrize("prec", [C64, C128])
+@pytest.mark.parametrize("k", [4, 5])
+def test_dense_k4_k5_matrix_cores_20q(prec, k):
+    """Control-free 4- and 5-target gates (the matrix-core path) on 20
+    qubits with targets in every order, including the lowest and highest
+    qubit."""
+    n = 20
+    rng = np.random.default_rng(40 + k)
+    v = random_state(n, 50 + k)
+    s = _state(n, prec, v)
+    want = v.copy()
+    for trial in range(5):
+        qs = [int(q) for q in rng.choice(n, k, replace=False)]
+        if trial == 0:
+            mid = [q for q in qs if q not in (0, n - 1)][:k - 2]
+            qs = [n - 1] + mid + [0]
+        u = _random_unitary(1 << k, rng)
+        s.apply_gate(qs, u)
+        want = oracle.apply_gate(want, n, u, qs, [])
+    _check_amps(s.get(), want, prec, f"k={k}")
+    s.free()
+
+
+@pytest.mark.parametrize("prec", [C64, C128])
 def test_diagonal_gates(prec):
     n = 11
     rng = np.random.default_rng(4)
