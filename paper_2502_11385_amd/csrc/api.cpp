@@ -315,6 +315,38 @@ qsv_status qsv_init_basis(qsv_state s, uint64_t index) {
   return QSV_OK;
 }
 
+// A control-free dense gate as a block for the matrix-core kernel: q gets
+// its targets in ascending order (block bit j = j-th smallest target) and
+// m its matrix re-indexed to that order.
+static void block_matrix(const HostGate& g, int32_t* q,
+                         std::vector<double>* m) {
+  const int d = 1 << g.k;
+  for (int j = 0; j < g.k; ++j) q[j] = g.t[j];
+  std::sort(q, q + g.k);
+  int pos[kMaxK] = {0};
+  for (int i = 0; i < g.k; ++i)
+    for (int j = 0; j < g.k; ++j)
+      if (q[j] == g.t[i]) pos[i] = j;
+  auto perm = [&](int r) {
+    int v = 0;
+    for (int i = 0; i < g.k; ++i) v |= ((r >> i) & 1) << pos[i];
+    return v;
+  };
+  m->assign(size_t(2) * d * d, 0.0);
+  for (int r = 0; r < d; ++r)
+    for (int c = 0; c < d; ++c) {
+      const size_t src = size_t(2) * (r * d + c);
+      const size_t dst = size_t(2) * (perm(r) * d + perm(c));
+      (*m)[dst] = g.m[src];
+      (*m)[dst + 1] = g.m[src + 1];
+    }
+}
+
+// Gates that take the matrix-core path when run on their own.
+static bool block_gate(const HostGate& g) {
+  return !g.diagonal && g.k >= 4 && g.c == 0;
+}
+
 qsv_status qsv_apply_gate(qsv_state s, const int32_t* targets, int32_t k,
                           const int32_t* controls, int32_t c,
                           const double* matrix) {
@@ -335,32 +367,12 @@ qsv_status qsv_apply_gate(qsv_state s, const int32_t* targets, int32_t k,
   if ((st = select_device(s)) != QSV_OK) return st;
   if (g.diagonal) {
     QSV_HIP(s, launch_diag(s->prec, s->amp, s->n, g, s->stream));
-  } else if (g.k >= 4 && g.c == 0) {
+  } else if (block_gate(g)) {
     // 4-5 targets without controls: the matrix-core block kernel of the
-    // fused plans, with the matrix re-indexed to ascending target order
-    // (block bit j = j-th smallest target) and, for complex64, rounded
-    // once to FP32
-    const int d = 1 << g.k;
+    // fused plans (the matrix rounded once to FP32 for complex64)
     int32_t q[kMaxK];
-    for (int j = 0; j < g.k; ++j) q[j] = g.t[j];
-    std::sort(q, q + g.k);
-    int pos[kMaxK];
-    for (int i = 0; i < g.k; ++i)
-      for (int j = 0; j < g.k; ++j)
-        if (q[j] == g.t[i]) pos[i] = j;
-    auto perm = [&](int r) {
-      int v = 0;
-      for (int i = 0; i < g.k; ++i) v |= ((r >> i) & 1) << pos[i];
-      return v;
-    };
-    std::vector<double> mp(size_t(2) * d * d);
-    for (int r = 0; r < d; ++r)
-      for (int c2 = 0; c2 < d; ++c2) {
-        const size_t src = size_t(2) * (r * d + c2);
-        const size_t dst = size_t(2) * (perm(r) * d + perm(c2));
-        mp[dst] = g.m[src];
-        mp[dst + 1] = g.m[src + 1];
-      }
+    std::vector<double> mp;
+    block_matrix(g, q, &mp);
     if (s->prec == QSV_C64) {
       std::vector<float> mf(mp.begin(), mp.end());
       if ((st = upload(s, mf.data(), mf.size() * sizeof(float))) != QSV_OK)
@@ -425,6 +437,9 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
   std::vector<FusedGate> fgates;
   std::vector<double> mats;             // gate matrices (FP64)
   std::vector<int64_t> plain_moff(plan.passes.size(), -1);
+  // plain passes run as one-gate matrix-core blocks (k = 0: not one)
+  std::vector<FusedBlock> plain_block(plan.passes.size(), FusedBlock{});
+  std::vector<float> plain32;  // their FP32 matrices, after the fused ones
   size_t u64_total = 0, u32_total = 0;  // fused outputs (in doubles/floats)
 
   for (size_t pi = 0; pi < plan.passes.size(); ++pi) {
@@ -435,7 +450,18 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
       if (!err.empty()) return fail(QSV_ERR_DEVICE, err);
     } else if (p.kind == kPassPlain) {
       const HostGate& g = G[p.gates[0]];
-      if (!g.diagonal && g.k >= 3) {
+      if (block_gate(g)) {
+        // as a single-gate block on the matrix cores, like qsv_apply_gate
+        std::vector<double> mp;
+        FusedBlock fb = {};
+        fb.k = g.k;
+        block_matrix(g, fb.q, &mp);
+        fb.u64_offset = int64_t(mats.size());
+        fb.u32_offset = int64_t(plain32.size());
+        mats.insert(mats.end(), mp.begin(), mp.end());
+        plain32.insert(plain32.end(), mp.begin(), mp.end());
+        plain_block[pi] = fb;
+      } else if (!g.diagonal && g.k >= 3) {
         plain_moff[pi] = int64_t(mats.size());
         mats.insert(mats.end(), g.m.begin(), g.m.end());
       }
@@ -473,6 +499,9 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
   for (auto& fb : fblocks) fb.u64_offset += int64_t(gate_doubles);
   mats.resize(gate_doubles + u64_total, 0.0);
   std::vector<float> mats32(u32_total, 0.0f);
+  for (auto& fb : plain_block)
+    if (fb.k) fb.u32_offset += int64_t(u32_total);
+  mats32.insert(mats32.end(), plain32.begin(), plain32.end());
 
   std::vector<char> buf;
   const size_t o_tp = put(buf, tpasses.data(), tpasses.size());
@@ -526,9 +555,16 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
       ++ti;
     } else if (p.kind == kPassPlain) {
       const HostGate& g = G[p.gates[0]];
-      if (g.diagonal)
+      const FusedBlock& pb = plain_block[pi];
+      if (g.diagonal) {
         QSV_HIP(s, launch_diag(s->prec, s->amp, n, g, s->stream));
-      else
+      } else if (pb.k) {
+        const void* u = s->prec == QSV_C64
+                            ? static_cast<const void*>(d_m32 + pb.u32_offset)
+                            : static_cast<const void*>(d_m64 + pb.u64_offset);
+        QSV_HIP(s, launch_fused_apply(s->prec, s->amp, n, pb.k, pb.q, u,
+                                      s->stream));
+      } else
         QSV_HIP(s, launch_dense(s->prec, s->amp, n, g,
                                 plain_moff[pi] >= 0 ? d_m64 + plain_moff[pi]
                                                     : nullptr,

@@ -63,13 +63,13 @@ def _unitary(d, rng):
 
 
 def random_gates(n, count, rng):
-    """Gates of every form the library accepts: dense 1..3-target unitaries
+    """Gates of every form the library accepts: dense 1..5-target unitaries
     with 0..2 controls, unitary diagonals, masked phases and diagonals that
     are not phases.  Returns [(matrix, targets, controls)]."""
     out = []
     for _ in range(count):
         kind = int(rng.integers(0, 9))
-        k = 1 if kind < 4 else int(rng.integers(1, 4))
+        k = 1 if kind < 4 else int(rng.integers(1, 6))
         c = int(rng.integers(0, 3))
         c = min(c, n - k)
         qs = [int(v) for v in rng.choice(n, k + c, replace=False)]

@@ -1,6 +1,6 @@
 """Randomised parity sweep: seeded random gate lists of every form the
-library accepts (dense 1..3-target unitaries with 0..2 controls, unitary
-diagonals on 1..3 qubits with and without controls, masked phases,
+library accepts (dense 1..5-target unitaries with 0..2 controls, unitary
+diagonals on 1..5 qubits with and without controls, masked phases,
 non-unitary diagonals), random plan options within the documented ranges,
 both precisions, against the oracle applying every gate in order.
 
