@@ -186,10 +186,12 @@ qsv_status qsv_plan_describe(const qsv_circuit* circ, int32_t n_qubits,
                              int32_t* n_passes);
 
 /* Host-only dry run of the device program (no device work): plans the
- * circuit as qsv_apply_fused would and builds its tile programs, then
- * writes out[0] passes, out[1] tile passes, out[2] tile segments,
- * out[3] tile ops, out[4] phase blocks, out[5] diagonal gates inside
- * phase blocks.  n_out <= 6 entries. */
+ * circuit as qsv_apply_fused would (the cache-blocking transpilation of
+ * Section III.B) and builds its tile programs, then writes out[0] passes,
+ * out[1] tile passes, out[2] tile segments, out[3] tile ops, out[4] phase
+ * blocks, out[5] diagonal gates inside phase blocks (host array; n_out <= 6
+ * entries).  QSV_ERR_UNSUPPORTED for an unknown precision,
+ * QSV_ERR_INVALID_ARG for a bad circuit, option, n_qubits or buffer. */
 qsv_status qsv_plan_program_stats(const qsv_circuit* circ, int32_t n_qubits,
                                   int32_t prec, const qsv_fuse_opts* opts,
                                   uint64_t* out, int32_t n_out);
