@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <array>
 #include <map>
 #include <tuple>
 
@@ -373,6 +374,9 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
   };
   // mux qubit and dense target of each op emitted in this pass (-1: none)
   std::vector<int> op_mux_q, op_target_q;
+  // pending (deferred) one-target products per qubit
+  std::vector<std::array<double, 8>> pp(n_q);
+  std::vector<char> has_pp(n_q, 0);
   auto emit_diag_tracked = [&](const HostGate& g) {
     emit_diag(g);
     op_mux_q.push_back(-1);
@@ -495,6 +499,109 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
     op_target_q.push_back(-1);
     touch_op(touched, int(tops->size()) - 1);
   };
+  // Emit (or merge) a dense one-target op with mux matrices M on target t:
+  // merged into the previous op on t when no op emitted since touches t
+  // and the mux qubit cannot have changed in between, else appended.
+  // With `defer`, an op without a mux that cannot merge is kept pending on
+  // t instead (see below).  Returns an error text or "".
+  auto put_dense = [&](int t, int mux_q, double (*M)[8], const Pass::Seg& sg,
+                       bool defer) -> std::string {
+    const int lb = local_of[t];
+    int reg = -1;
+    for (int i = 0; i < RB; ++i)
+      if (sg.reg_bits[i] == lb) reg = i;
+    if (reg < 0) return "internal planner error: target not in a register bit";
+    const int prev = last_touch[t];
+    if (prev >= op_base) {
+      TileOp& po = (*tops)[prev];
+      const int pq = op_mux_q[prev - op_base];
+      if (po.kind == kOpDense1 && op_target_q[prev - op_base] == t &&
+          po.lctrl == 0 && po.gctrl == 0 &&
+          (pq < 0 || mux_q < 0 || pq == mux_q) &&
+          (mux_q < 0 || last_dense[mux_q] < prev)) {
+        const int mq = pq >= 0 ? pq : mux_q;
+        double out[2][8];
+        for (int v = 0; v < 2; ++v) {
+          const double* A = M[v];
+          const double* B = (pq >= 0 && v) ? po.m2 : po.m;
+          for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) {
+              double cr = 0, ci = 0;
+              for (int k = 0; k < 2; ++k) {
+                const double ar = A[2 * (2 * r + k)], ai = A[2 * (2 * r + k) + 1];
+                const double br = B[2 * (2 * k + c)], bi = B[2 * (2 * k + c) + 1];
+                cr += ar * br - ai * bi;
+                ci += ar * bi + ai * br;
+              }
+              out[v][2 * (2 * r + c)] = cr;
+              out[v][2 * (2 * r + c) + 1] = ci;
+            }
+        }
+        std::memcpy(po.m, out[0], sizeof out[0]);
+        std::memcpy(po.m2, out[1], sizeof out[1]);
+        po.mux = mux_code(mq);
+        op_mux_q[prev - op_base] = mq;
+        for (int e = 0; e < 8; ++e) {
+          po.mf[e] = float(po.m[e]);
+          po.mf2[e] = float(po.m2[e]);
+        }
+        if (mq >= 0) touch_op(uint64_t(1) << mq, prev);
+        last_dense[t] = std::max(last_dense[t], prev);
+        return "";
+      }
+    }
+    if (defer && mux_q < 0) {
+      std::memcpy(pp[t].data(), M[0], sizeof M[0]);
+      has_pp[t] = 1;
+      return "";
+    }
+    TileOp op = {};
+    op.kind = kOpDense1;
+    op.reg = reg;
+    std::memcpy(op.m, M[0], sizeof op.m);
+    std::memcpy(op.m2, M[1], sizeof op.m2);
+    op.mux = mux_code(mux_q);
+    for (int e = 0; e < 8; ++e) {
+      op.mf[e] = float(op.m[e]);
+      op.mf2[e] = float(op.m2[e]);
+    }
+    tops->push_back(op);
+    op_mux_q.push_back(mux_q);
+    op_target_q.push_back(t);
+    const int idx = int(tops->size()) - 1;
+    touch_op((uint64_t(1) << t) | (mux_q >= 0 ? uint64_t(1) << mux_q : 0), idx);
+    last_dense[t] = idx;
+    return "";
+  };
+  // Deferred one-target gates.  A dense gate without controls whose op would
+  // have no mux, and that cannot merge into the previous op on its target,
+  // is kept as a pending 2x2 product on the target instead of being
+  // emitted: the next dense gate on that target absorbs it (M <- M P), so a
+  // gate between two controlled-phase folds joins one op.  A pending product
+  // is emitted first wherever its qubit must be settled: before an op that
+  // uses the qubit as its mux or a control, before a diagonal run touching
+  // it, and at the end of its segment.
+  auto flush = [&](int q, const Pass::Seg& sg) -> std::string {
+    if (!has_pp[q]) return "";
+    has_pp[q] = 0;
+    double M[2][8];
+    std::memcpy(M[0], pp[q].data(), sizeof M[0]);
+    std::memcpy(M[1], pp[q].data(), sizeof M[1]);
+    return put_dense(q, -1, M, sg, false);
+  };
+  auto flush_mask = [&](uint64_t mask, const Pass::Seg& sg) -> std::string {
+    for (int q = 0; q < n_q; ++q)
+      if (mask >> q & 1) {
+        std::string e = flush(q, sg);
+        if (!e.empty()) return e;
+      }
+    return "";
+  };
+  auto touched_by = [&](const std::vector<int>& ds) {
+    uint64_t m = 0;
+    for (int d : ds) m |= G[d].touch();
+    return m;
+  };
   std::vector<int> pend;
   for (size_t si = 0; si < p.segs.size(); ++si) {
     const auto& sg = p.segs[si];
@@ -514,7 +621,7 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
       pend.swap(keep);
       // the gate as mux matrices
       int mux_q = -1;
-      bool plain = g.c > 1;  // more than one control: a controlled op
+      const bool plain = g.c > 1;  // more than one control: a controlled op
       double M[2][8];
       if (g.c == 1) {
         mux_q = g.ctl[0];
@@ -535,7 +642,10 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
           else if (mux_q != q) fold = false;
         }
       }
+      std::string err;
       if (!fold) {
+        // the pending products of the run's qubits precede it
+        if (!(err = flush_mask(touched_by(hit), sg)).empty()) return err;
         emit_diag_run(hit, sg);
         if (!plain && g.c == 0) mux_q = -1;
         if (!plain && g.c == 1) mux_q = g.ctl[0];
@@ -560,82 +670,63 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
             }
           }
       }
-      const int lb = local_of[t];
-      int reg = -1;
-      for (int i = 0; i < RB; ++i)
-        if (sg.reg_bits[i] == lb) reg = i;
-      if (reg < 0) return "internal planner error: target not in a register bit";
-      // merge into the previous op on t?
-      const int prev = last_touch[t];
-      bool merged = false;
-      if (!plain && prev >= op_base) {
-        TileOp& po = (*tops)[prev];
-        const int pq = op_mux_q[prev - op_base];
-        if (po.kind == kOpDense1 && op_target_q[prev - op_base] == t &&
-            po.lctrl == 0 && po.gctrl == 0 &&
-            (pq < 0 || mux_q < 0 || pq == mux_q)) {
-          const int mq = pq >= 0 ? pq : mux_q;
-          // the mux qubit must keep its value from prev to here
-          const bool ok = mux_q < 0 || last_dense[mux_q] < prev;
-          if (ok) {
-            double out[2][8];
-            for (int v = 0; v < 2; ++v) {
-              const double* A = M[v];
-              const double* B = (pq >= 0 && v) ? po.m2 : po.m;
-              double* C2 = out[v];
-              for (int r = 0; r < 2; ++r)
-                for (int c = 0; c < 2; ++c) {
-                  double cr = 0, ci = 0;
-                  for (int k = 0; k < 2; ++k) {
-                    const double ar = A[2 * (2 * r + k)], ai = A[2 * (2 * r + k) + 1];
-                    const double br = B[2 * (2 * k + c)], bi = B[2 * (2 * k + c) + 1];
-                    cr += ar * br - ai * bi;
-                    ci += ar * bi + ai * br;
-                  }
-                  C2[2 * (2 * r + c)] = cr;
-                  C2[2 * (2 * r + c) + 1] = ci;
-                }
-            }
-            std::memcpy(po.m, out[0], sizeof out[0]);
-            std::memcpy(po.m2, out[1], sizeof out[1]);
-            po.mux = mux_code(mq);
-            op_mux_q[prev - op_base] = mq;
-            for (int e = 0; e < 8; ++e) {
-              po.mf[e] = float(po.m[e]);
-              po.mf2[e] = float(po.m2[e]);
-            }
-            if (mq >= 0) touch_op(uint64_t(1) << mq, prev);
-            merged = true;
-          }
-        }
-      }
-      if (!merged) {
+      if (plain) {
+        // a controlled op: its target and controls are settled first
+        if (!(err = flush_mask(g.touch(), sg)).empty()) return err;
+        const int lb = local_of[t];
+        int reg = -1;
+        for (int i = 0; i < RB; ++i)
+          if (sg.reg_bits[i] == lb) reg = i;
+        if (reg < 0) return "internal planner error: target not in a register bit";
         TileOp op = {};
         op.kind = kOpDense1;
         op.reg = reg;
         op.mux = kMuxNone;
-        if (plain) {
-          place_ctrl(&op, g.cmask);
-          for (int e = 0; e < 8; ++e) op.m[e] = g.m[e];
-        } else {
-          std::memcpy(op.m, M[0], sizeof op.m);
-          std::memcpy(op.m2, M[1], sizeof op.m2);
-          op.mux = mux_code(mux_q);
-        }
+        place_ctrl(&op, g.cmask);
         for (int e = 0; e < 8; ++e) {
+          op.m[e] = g.m[e];
           op.mf[e] = float(op.m[e]);
-          op.mf2[e] = float(op.m2[e]);
         }
         tops->push_back(op);
-        op_mux_q.push_back(plain ? -1 : mux_q);
+        op_mux_q.push_back(-1);
         op_target_q.push_back(t);
         const int idx = int(tops->size()) - 1;
-        touch_op(g.touch() | (mux_q >= 0 ? uint64_t(1) << mux_q : 0), idx);
+        touch_op(g.touch(), idx);
         last_dense[t] = idx;
-      } else {
-        last_dense[t] = std::max(last_dense[t], prev);
+        continue;
       }
+      // absorb the target's pending product (applied before this gate)
+      if (has_pp[t]) {
+        has_pp[t] = 0;
+        for (int v = 0; v < 2; ++v) {
+          double out[8];
+          const double* A = M[v];
+          const double* B = pp[t].data();
+          for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) {
+              double cr = 0, ci = 0;
+              for (int k = 0; k < 2; ++k) {
+                const double ar = A[2 * (2 * r + k)], ai = A[2 * (2 * r + k) + 1];
+                const double br = B[2 * (2 * k + c)], bi = B[2 * (2 * k + c) + 1];
+                cr += ar * br - ai * bi;
+                ci += ar * bi + ai * br;
+              }
+              out[2 * (2 * r + c)] = cr;
+              out[2 * (2 * r + c) + 1] = ci;
+            }
+          std::memcpy(M[v], out, sizeof out);
+        }
+      }
+      // the mux qubit is settled before an op that reads it
+      if (mux_q >= 0 && !(err = flush(mux_q, sg)).empty()) return err;
+      if (!(err = put_dense(t, mux_q, M, sg, true)).empty()) return err;
     }
+    // a pending product may wait into the next segment only if its qubit is
+    // a register bit there too
+    uint64_t keep_q = 0;
+    if (si + 1 < p.segs.size())
+      for (int i = 0; i < RB; ++i) keep_q |= uint64_t(1) << p.q[p.segs[si + 1].reg_bits[i]];
+    if (std::string err = flush_mask(~keep_q, sg); !err.empty()) return err;
     if (si + 1 == p.segs.size()) {
       emit_diag_run(pend, sg);
       pend.clear();
