@@ -374,9 +374,13 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
   };
   // mux qubit and dense target of each op emitted in this pass (-1: none)
   std::vector<int> op_mux_q, op_target_q;
-  // pending (deferred) one-target products per qubit
+  // pending (deferred) one-target products per qubit, and the segment
+  // (pass-local index) where each would be emitted
   std::vector<std::array<double, 8>> pp(n_q);
   std::vector<char> has_pp(n_q, 0);
+  std::vector<int> pp_seg(n_q, -1);
+  int cur_si = 0;          // the segment being emitted
+  TileSeg* cur_ts = nullptr;
   auto emit_diag_tracked = [&](const HostGate& g) {
     emit_diag(g);
     op_mux_q.push_back(-1);
@@ -504,12 +508,12 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
   // and the mux qubit cannot have changed in between, else appended.
   // With `defer`, an op without a mux that cannot merge is kept pending on
   // t instead (see below).  Returns an error text or "".
-  auto put_dense = [&](int t, int mux_q, double (*M)[8], const Pass::Seg& sg,
+  auto put_dense = [&](int t, int mux_q, double (*M)[8], int seg_idx,
                        bool defer) -> std::string {
     const int lb = local_of[t];
     int reg = -1;
     for (int i = 0; i < RB; ++i)
-      if (sg.reg_bits[i] == lb) reg = i;
+      if (p.segs[seg_idx].reg_bits[i] == lb) reg = i;
     if (reg < 0) return "internal planner error: target not in a register bit";
     const int prev = last_touch[t];
     if (prev >= op_base) {
@@ -553,6 +557,7 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
     if (defer && mux_q < 0) {
       std::memcpy(pp[t].data(), M[0], sizeof M[0]);
       has_pp[t] = 1;
+      pp_seg[t] = seg_idx;
       return "";
     }
     TileOp op = {};
@@ -565,12 +570,37 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
       op.mf[e] = float(op.m[e]);
       op.mf2[e] = float(op.m2[e]);
     }
-    tops->push_back(op);
-    op_mux_q.push_back(mux_q);
-    op_target_q.push_back(t);
-    const int idx = int(tops->size()) - 1;
-    touch_op((uint64_t(1) << t) | (mux_q >= 0 ? uint64_t(1) << mux_q : 0), idx);
-    last_dense[t] = idx;
+    if (seg_idx == cur_si) {
+      tops->push_back(op);
+      op_mux_q.push_back(mux_q);
+      op_target_q.push_back(t);
+      const int idx = int(tops->size()) - 1;
+      touch_op((uint64_t(1) << t) | (mux_q >= 0 ? uint64_t(1) << mux_q : 0), idx);
+      last_dense[t] = idx;
+      return "";
+    }
+    // An earlier, closed segment (a pending product whose qubit is not a
+    // register bit of the current segment; mux_q < 0): the op goes at that
+    // segment's end.  Nothing emitted since touches t, so the op commutes
+    // with everything after it; every later index moves up by one.
+    const int pos = (*tsegs)[size_t(tp.seg_begin) + size_t(seg_idx)].op_end;
+    tops->insert(tops->begin() + pos, op);
+    op_mux_q.insert(op_mux_q.begin() + (pos - op_base), -1);
+    op_target_q.insert(op_target_q.begin() + (pos - op_base), t);
+    for (int& v : last_touch)
+      if (v >= pos) ++v;
+    for (int& v : last_dense)
+      if (v >= pos) ++v;
+    for (Blob& bl : blobs)
+      if (bl.op >= pos) ++bl.op;
+    for (int k = seg_idx; k < cur_si; ++k) {
+      TileSeg& T = (*tsegs)[size_t(tp.seg_begin) + size_t(k)];
+      if (k > seg_idx) ++T.op_begin;
+      ++T.op_end;
+    }
+    ++cur_ts->op_begin;
+    last_touch[t] = pos;
+    last_dense[t] = pos;
     return "";
   };
   // Deferred one-target gates.  A dense gate without controls whose op would
@@ -580,19 +610,21 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
   // gate between two controlled-phase folds joins one op.  A pending product
   // is emitted first wherever its qubit must be settled: before an op that
   // uses the qubit as its mux or a control, before a diagonal run touching
-  // it, and at the end of its segment.
-  auto flush = [&](int q, const Pass::Seg& sg) -> std::string {
+  // it, and by the pass's end.  It may wait across segments; when settled it
+  // goes into the latest segment so far that holds its qubit in a register
+  // bit (at that segment's end when the segment is already closed).
+  auto flush = [&](int q) -> std::string {
     if (!has_pp[q]) return "";
     has_pp[q] = 0;
     double M[2][8];
     std::memcpy(M[0], pp[q].data(), sizeof M[0]);
     std::memcpy(M[1], pp[q].data(), sizeof M[1]);
-    return put_dense(q, -1, M, sg, false);
+    return put_dense(q, -1, M, pp_seg[q], false);
   };
-  auto flush_mask = [&](uint64_t mask, const Pass::Seg& sg) -> std::string {
+  auto flush_mask = [&](uint64_t mask) -> std::string {
     for (int q = 0; q < n_q; ++q)
       if (mask >> q & 1) {
-        std::string e = flush(q, sg);
+        std::string e = flush(q);
         if (!e.empty()) return e;
       }
     return "";
@@ -608,6 +640,14 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
     TileSeg ts = {};
     for (int i = 0; i < RB; ++i) ts.reg_bits[i] = sg.reg_bits[i];
     ts.op_begin = int32_t(tops->size());
+    cur_si = int(si);
+    cur_ts = &ts;
+    // a pending product is emitted as late as possible: in the latest
+    // segment so far that holds its qubit in a register bit
+    for (int i = 0; i < RB; ++i) {
+      const int q = p.q[sg.reg_bits[i]];
+      if (has_pp[q]) pp_seg[q] = int(si);
+    }
     for (int gi : sg.gates) {
       const HostGate& g = G[gi];
       if (g.diagonal) {
@@ -645,7 +685,7 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
       std::string err;
       if (!fold) {
         // the pending products of the run's qubits precede it
-        if (!(err = flush_mask(touched_by(hit), sg)).empty()) return err;
+        if (!(err = flush_mask(touched_by(hit))).empty()) return err;
         emit_diag_run(hit, sg);
         if (!plain && g.c == 0) mux_q = -1;
         if (!plain && g.c == 1) mux_q = g.ctl[0];
@@ -672,7 +712,7 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
       }
       if (plain) {
         // a controlled op: its target and controls are settled first
-        if (!(err = flush_mask(g.touch(), sg)).empty()) return err;
+        if (!(err = flush_mask(g.touch())).empty()) return err;
         const int lb = local_of[t];
         int reg = -1;
         for (int i = 0; i < RB; ++i)
@@ -718,16 +758,13 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
         }
       }
       // the mux qubit is settled before an op that reads it
-      if (mux_q >= 0 && !(err = flush(mux_q, sg)).empty()) return err;
-      if (!(err = put_dense(t, mux_q, M, sg, true)).empty()) return err;
+      if (mux_q >= 0 && !(err = flush(mux_q)).empty()) return err;
+      if (!(err = put_dense(t, mux_q, M, int(si), true)).empty()) return err;
     }
-    // a pending product may wait into the next segment only if its qubit is
-    // a register bit there too
-    uint64_t keep_q = 0;
-    if (si + 1 < p.segs.size())
-      for (int i = 0; i < RB; ++i) keep_q |= uint64_t(1) << p.q[p.segs[si + 1].reg_bits[i]];
-    if (std::string err = flush_mask(~keep_q, sg); !err.empty()) return err;
+    // pending products wait across segments (the next dense gate on the
+    // qubit may absorb them); the pass's end settles every one of them
     if (si + 1 == p.segs.size()) {
+      if (std::string err = flush_mask(~uint64_t(0)); !err.empty()) return err;
       emit_diag_run(pend, sg);
       pend.clear();
     }
