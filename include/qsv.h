@@ -129,7 +129,7 @@ typedef enum {
  *                L - reg_log2 <= 9 (default 12)
  *   k_max      : widest fused block, 1..5 (default 5)
  *   low_qubits : qubits 0..low_qubits-1 belong to every tile so that HBM
- *                accesses are contiguous runs (default 5 c64, 4 c128)
+ *                accesses are contiguous runs (default 4)
  *   reg_log2   : amplitudes per thread inside a tile, as log2: 3, 4 or 5
  *                (5 for c64 only; default 4)
  * This is the single-GPU form of the chunking and cache blocking of

@@ -68,6 +68,10 @@ __device__ __forceinline__ void batch_phase_body(
     // part; a variant has at most 2^24 amplitudes, so every offset inside
     // its state or its output fits 32 bits
     const uint32_t thr = active ? io_thread_index<RB>(pass, tid) : 0u;
+    // the load test is uniform over the wave (inactive lanes of a partly
+    // active wave read the tile's first element, in bounds, and their
+    // registers are never written back), so the loads issue back to back
+    const bool wave_on = __ballot(active) != 0;
     uint64_t roff[R];
     io_reg_offsets<C, RB>(pass, roff);  // bytes of C
     const uint64_t end = run_end < hi ? run_end : hi;
@@ -77,12 +81,14 @@ __device__ __forceinline__ void batch_phase_body(
       for (int b = 0; b < L; ++b) base = insert_zero64(base, pass->q[b]);
       const char* sb = reinterpret_cast<const char*>(state + base);
       C a[R];
+      if (!first && wave_on) {
 #pragma unroll
-      for (int j = 0; j < R; ++j) {
-        if (!first && active) {
+        for (int j = 0; j < R; ++j)
           a[j] = load_at(state, raw_rsrc<C>(sb + roff[j]),
                          thr * uint32_t(sizeof(C)));
-        } else {
+      } else {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
           const bool one = first && active && base == 0 && roff[j] == 0 &&
                            thr == 0;
           a[j].x = one ? T(1) : T(0);

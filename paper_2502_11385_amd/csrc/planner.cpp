@@ -28,7 +28,7 @@ std::string resolve_options(int n, int bytes_per_amp, const int* v,
   r.strategy = v ? v[0] : 0;
   r.tile_log2 = (v && v[1]) ? v[1] : 12;
   r.k_max = (v && v[2]) ? v[2] : 5;
-  r.low_qubits = (v && v[3]) ? v[3] : (bytes_per_amp == 8 ? 5 : 4);
+  r.low_qubits = (v && v[3]) ? v[3] : 4;
   r.reg_log2 = (v && v[4]) ? v[4] : 4;
   if (r.strategy < 0 || r.strategy > 3) return "unknown strategy";
   if (r.tile_log2 < 8 || r.tile_log2 > 13) return "tile_log2 must be 8..13";

@@ -49,7 +49,7 @@ struct PlanOptions {
   int strategy = 0;     // qsv_strategy
   int tile_log2 = 12;
   int k_max = 5;
-  int low_qubits = 5;
+  int low_qubits = 4;
   int reg_log2 = 4;
 };
 

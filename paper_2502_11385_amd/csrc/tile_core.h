@@ -385,11 +385,23 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
   Layout<RB> cur = io;
   const int nseg = pass->nseg;
   const TileSeg* sp = segs + pass->seg_begin;
+  // complex64 amplitudes are carried as 64-bit values, so the copies where
+  // the ops' arms and the segments join move register pairs
+  using W64 = std::conditional_t<sizeof(T) == 4, uint64_t, C>;
+  W64 w[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) w[j] = __builtin_bit_cast(W64, a[j]);
   for (int s = 0; s < nseg; ++s) {
     Layout<RB> lay;
 #pragma unroll
     for (int i = 0; i < RB; ++i) lay.rb[i] = sp[s].reg_bits[i];
-    if (!same_layout(cur, lay)) relayout<T, RB>(a, lds, cur, lay, tid, active);
+    if (!same_layout(cur, lay)) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) a[j] = __builtin_bit_cast(C, w[j]);
+      relayout<T, RB>(a, lds, cur, lay, tid, active);
+#pragma unroll
+      for (int j = 0; j < R; ++j) w[j] = __builtin_bit_cast(W64, a[j]);
+    }
     cur = lay;
     const uint32_t rt = thread_local_base(lay, tid);
     uint32_t lr[R];
@@ -397,6 +409,8 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
     for (int j = 0; j < R; ++j) lr[j] = reg_offset(lay, j);
 
     for (int o = sp[s].op_begin; o < sp[s].op_end; ++o) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) a[j] = __builtin_bit_cast(C, w[j]);
       const TileOp* op = ops + o;
       // Read the header and both matrices before any branch, so that the
       // scalar loads issue together and the op waits for them once (a
@@ -496,8 +510,12 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
           a[j] = csel(on, y, a[j]);
         }
       }
+#pragma unroll
+      for (int j = 0; j < R; ++j) w[j] = __builtin_bit_cast(W64, a[j]);
     }
   }
+#pragma unroll
+  for (int j = 0; j < R; ++j) a[j] = __builtin_bit_cast(C, w[j]);
   if (!same_layout(cur, io)) relayout<T, RB>(a, lds, cur, io, tid, active);
 }
 
