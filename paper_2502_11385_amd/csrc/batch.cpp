@@ -116,7 +116,7 @@ std::string append_variant(int w, const std::vector<HostGate>& G, int b,
     PlanOptions po;
     po.strategy = 2;
     po.tile_log2 = std::min(L, w);
-    po.low_qubits = std::min(b == 8 ? 5 : 4, po.tile_log2 - 1);
+    po.low_qubits = std::min(4, po.tile_log2 - 1);
     po.reg_log2 = RB;
     Plan plan;
     make_plan(G, w, b, po, &plan);
