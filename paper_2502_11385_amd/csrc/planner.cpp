@@ -176,24 +176,54 @@ static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
         local_of[q] = j++;
       }
     // Register segments: the same greedy scan over tile-local target bits
-    // with capacity RB; diagonal gates need no register bit.
-    std::vector<int> seg_pending = taken;
-    while (!seg_pending.empty()) {
-      uint64_t S = 0;
-      std::vector<int> seg_gates;
-      greedy(G, &seg_pending, &S, RB,
-             [&](const HostGate& g) -> uint64_t {
-               return g.diagonal ? 0 : (1ull << local_of[g.t[0]]);
-             },
-             [](const HostGate&) { return true; }, &seg_gates);
-      // Fill the register bits with the highest unused tile-local bits so
-      // that the low bits index lanes (contiguous HBM runs across lanes).
-      for (int lb = L - 1; lb >= 0 && popc(S) < RB; --lb) S |= 1ull << lb;
-      Pass::Seg sg;
-      for (int lb = 0, j = 0; lb < L; ++lb)
-        if (S >> lb & 1) sg.reg_bits[j++] = lb;
-      sg.gates = std::move(seg_gates);
-      p.segs.push_back(std::move(sg));
+    // with capacity RB; diagonal gates need no register bit.  Unused
+    // register bits are filled with the highest free tile-local bits, so
+    // that the low bits index lanes (contiguous HBM runs across lanes) and a
+    // segment that needs few bits tends to match the I/O layout (register
+    // bits L-RB..L-1), which saves the re-layout on entry or exit.
+    auto build_segs = [&](bool seed_io) {
+      std::vector<Pass::Seg> segs;
+      std::vector<int> seg_pending = taken;
+      bool first = true;
+      while (!seg_pending.empty()) {
+        // seed_io: the first segment takes the I/O layout's register bits
+        // and collects the gates that fit them
+        uint64_t S = (first && seed_io) ? ((1ull << RB) - 1) << (L - RB) : 0;
+        first = false;
+        std::vector<int> seg_gates;
+        greedy(G, &seg_pending, &S, RB,
+               [&](const HostGate& g) -> uint64_t {
+                 return g.diagonal ? 0 : (1ull << local_of[g.t[0]]);
+               },
+               [](const HostGate&) { return true; }, &seg_gates);
+        for (int lb = L - 1; lb >= 0 && popc(S) < RB; --lb) S |= 1ull << lb;
+        Pass::Seg sg;
+        for (int lb = 0, j = 0; lb < L; ++lb)
+          if (S >> lb & 1) sg.reg_bits[j++] = lb;
+        sg.gates = std::move(seg_gates);
+        segs.push_back(std::move(sg));
+      }
+      return segs;
+    };
+    // re-layouts a segment list costs: entry, between segments, exit
+    auto relayouts = [&](const std::vector<Pass::Seg>& segs) {
+      auto same = [&](const Pass::Seg& x, const int* rb) {
+        for (int i = 0; i < RB; ++i)
+          if (x.reg_bits[i] != rb[i]) return false;
+        return true;
+      };
+      int io[6];
+      for (int i = 0; i < RB; ++i) io[i] = L - RB + i;
+      int r = !same(segs.front(), io) + !same(segs.back(), io);
+      for (size_t i = 1; i < segs.size(); ++i)
+        r += !same(segs[i], segs[i - 1].reg_bits);
+      return r;
+    };
+    // the plain scan, or the seeded one where it needs fewer re-layouts
+    p.segs = build_segs(false);
+    if (!p.segs.empty()) {
+      std::vector<Pass::Seg> seeded = build_segs(true);
+      if (relayouts(seeded) < relayouts(p.segs)) p.segs.swap(seeded);
     }
     for (const auto& sg : p.segs)
       p.gates.insert(p.gates.end(), sg.gates.begin(), sg.gates.end());
