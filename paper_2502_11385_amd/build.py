@@ -33,6 +33,15 @@ DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 # constant register-array indices into dynamic ones, which forces the
 # register-resident tile into scratch memory.
 NO_SINK = ["-mllvm", "-simplifycfg-sink-common=false"]
+# The register-tile kernels (tile passes, batch phases) also leave uniform
+# control flow unstructured: structurizing the op loop's uniform switch
+# (over an op's class and target register) into flow blocks with partly
+# undefined phis made the register allocator copy every amplitude register
+# after every op (32 moves per 128 FMAs).  Only these files, which the
+# parity suite covers op class by op class: the cut reconstruction kernels
+# gave wrong results with it.
+UNSTRUCTURED = ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]
+TILE_SOURCES = ("k_tile.hip", "k_batch.hip")
 
 
 def _compile(src: str) -> str:
@@ -40,6 +49,8 @@ def _compile(src: str) -> str:
     cmd = [HIPCC] + COMMON + DEVICE
     if src.endswith(".hip"):
         cmd += ["-x", "hip"] + NO_SINK
+        if src in TILE_SOURCES:
+            cmd += UNSTRUCTURED
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

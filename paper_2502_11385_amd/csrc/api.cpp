@@ -549,9 +549,8 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
       QSV_HIP(s, hipEventRecord(s->evs[2 * pi], s->stream));
     }
     if (p.kind == kPassTile) {
-      QSV_HIP(s, launch_tile(s->prec, po.reg_log2, s->amp, n, p.L,
-                             tpasses[ti].flags, d_tp + ti, d_ts, d_to,
-                             s->stream));
+      QSV_HIP(s, launch_tile(s->prec, po.reg_log2, s->amp, n, tpasses[ti],
+                             d_tp + ti, d_ts, d_to, s->stream));
       ++ti;
     } else if (p.kind == kPassPlain) {
       const HostGate& g = G[p.gates[0]];
@@ -766,17 +765,41 @@ qsv_status qsv_debug_emulate_tiled(const qsv_circuit* circ, int32_t n,
           if ((op.mux_reg >= 0) != mux_in_reg ||
               (op.mux_reg >= 0 && sg.reg_bits[op.mux_reg] != op.mux))
             return fail(QSV_ERR_DEVICE, "tile op has an inconsistent mux_reg");
+          // the ops run by their dispatch codes, as the kernels run them
+          const int cls = op.code >> 3, creg = op.code & 7;
+          const bool dense = cls <= kCodeCtrlMux;
+          if (dense != (op.kind == kOpDense1) ||
+              (dense && (creg != op.reg || creg >= po.reg_log2)) ||
+              (cls == kCodePhase && op.kind != kOpPhase) ||
+              (cls == kCodeDiag && op.kind != kOpDiag) ||
+              (cls == kCodePhaseBlock && op.kind != kOpPhaseBlock) ||
+              ((cls == kCodeUniform || cls == kCodeRegMux ||
+                cls == kCodeThreadMux) && op.lctrl != 0) ||
+              ((cls == kCodeUniform || cls == kCodeCtrl) &&
+               (op.arg < 0 || op.arg > 63)) ||
+              (cls == kCodeRegMux &&
+               (op.arg < 0 || op.arg >= po.reg_log2 || op.arg == creg)) ||
+              (cls == kCodeThreadMux &&
+               [&] {  // a thread bit: no register bit of the segment
+                 for (int i = 0; i < po.reg_log2; ++i)
+                   if (sg.reg_bits[i] == op.arg) return true;
+                 return op.arg < 0 || op.arg >= L;
+               }()))
+            return fail(QSV_ERR_DEVICE, "tile op has an inconsistent code");
           if ((base & op.gctrl) != op.gctrl) continue;
           for (uint32_t r = 0; r < (1u << L); ++r) {
             if ((r & op.lctrl) != op.lctrl) continue;
-            if (op.kind == kOpDense1) {
-              const int tb = sg.reg_bits[op.reg];
+            if (dense) {
+              const int tb = sg.reg_bits[creg];
               if (r >> tb & 1) continue;
               const uint32_t r1 = r | (1u << tb);
               bool second = false;
-              if (op.mux != kMuxNone)
-                second = op.mux >= 0 ? ((r >> op.mux) & 1)
-                                     : ((base >> (-1 - op.mux)) & 1);
+              if (cls == kCodeUniform || cls == kCodeCtrl)
+                second = (base >> op.arg) & 1;
+              else if (cls == kCodeRegMux)
+                second = (r >> sg.reg_bits[op.arg]) & 1;
+              else
+                second = (r >> op.arg) & 1;
               const double* m = second ? op.m2 : op.m;
               const std::complex<double> x0 = C(gidx(r)), x1 = C(gidx(r1));
               const std::complex<double> m00(m[0], m[1]), m01(m[2], m[3]),
@@ -817,7 +840,7 @@ qsv_status qsv_debug_emulate_tiled(const qsv_circuit* circ, int32_t n,
                 return db >= 0 ? int(r >> db & 1) : int(base >> (-1 - db) & 1);
               };
               int e = bit(op.dbit0);
-              if (op.dk > 1) e |= bit(op.dbit1) << 1;
+              if (op.arg > 1) e |= bit(op.dbit1) << 1;
               put(gidx(r), C(gidx(r)) *
                                std::complex<double>(op.m[2 * e], op.m[2 * e + 1]));
             }

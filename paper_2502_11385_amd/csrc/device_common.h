@@ -9,6 +9,22 @@
 
 namespace qsv {
 
+// The device program (passes, segments, ops, phase-block records) is read
+// through the constant address space.  The kernels never write it, and
+// uniform reads through such pointers are scalar loads even in loops that
+// also hold asm statements with memory clobbers (the LDS barriers and the
+// streaming kernel's DMA), where the compiler could no longer prove the
+// records unchanged and would read them with vector loads.
+template <typename R>
+using cptr = const __attribute__((address_space(4))) R*;
+template <typename R>
+__device__ __forceinline__ cptr<R> as_const(const R* p) {
+  return (cptr<R>)(p);
+}
+// 16 bytes of such a record as a plain vector (no constructors, so it loads
+// through a constant-address-space pointer on both compilation passes)
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
 template <typename T>
 struct CxT;
 template <>
@@ -77,11 +93,12 @@ hipError_t launch_dense(int prec, void* amp, int n, const HostGate& g,
 // Plain diagonal gate (any k, controls).
 hipError_t launch_diag(int prec, void* amp, int n, const HostGate& g,
                        hipStream_t stream);
-// One tile pass: pass/segs/ops point into the device program buffer;
-// L is the pass's tile size and rb its register bits.
-hipError_t launch_tile(int prec, int rb, void* amp, int n, int L,
-                       int32_t flags, const TilePass* pass, const TileSeg* segs,
-                       const TileOp* ops, hipStream_t stream);
+// One tile pass: pass/segs/ops point into the device program buffer,
+// host_pass is the host copy of *pass; rb is the register bits.
+hipError_t launch_tile(int prec, int rb, void* amp, int n,
+                       const TilePass& host_pass, const TilePass* pass,
+                       const TileSeg* segs, const TileOp* ops,
+                       hipStream_t stream);
 // Build all fused unitaries (FP64, then rounded to FP32).
 hipError_t launch_fused_build(const FusedBlock* blocks, int n_blocks,
                               const FusedGate* gates, double* mats64,

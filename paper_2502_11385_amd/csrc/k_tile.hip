@@ -15,6 +15,8 @@
 // This is the single-GPU form of the paper's chunking with cache blocking
 // (Section III.B): a tile is a 2^L-amplitude chunk, and a pass runs every
 // gate that the planner could move onto the chunk's qubits.
+#include <mutex>
+
 #include "tile_core.h"
 
 namespace qsv {
@@ -23,20 +25,29 @@ namespace qsv {
 // bits spread over the non-tile qubits.
 __device__ __forceinline__ uint64_t tile_base(const TilePass* pass,
                                               uint32_t tile) {
+  const cptr<TilePass> cp = as_const(pass);
   uint64_t base = tile;
-  const int L = pass->L;
-  for (int b = 0; b < L; ++b) base = insert_zero64(base, pass->q[b]);
+  const int L = cp->L;
+  for (int b = 0; b < L; ++b) base = insert_zero64(base, cp->q[b]);
   return base;
 }
 
-// One tile per work-group.  At most 512 threads per tile (L - RB <= 9).
-// BOFF32 as for the persistent kernel; otherwise 64-bit addressing.
-template <typename T, int RB, bool BOFF32>
+// One tile per work-group (at most 512 threads, L - RB <= 9).  HBM
+// transfers use the I/O layout: registers select the top RB tile bits and
+// consecutive threads take consecutive low tile bits, so a wave's accesses
+// are contiguous runs of the lowest (always tile) qubits.  A thread's
+// element index is base | lane part | wave part | register part, four
+// disjoint bit sets: the lane part (thread bits 0..5 spread over their tile
+// qubits) differs per lane, the others are uniform over a wave.  Each access
+// is therefore one wave-uniform 64-bit address plus a per-lane offset,
+// 32-bit where LANE32 says it fits (else 64-bit).
+template <typename T, int RB, bool LANE32>
 __device__ __forceinline__ void tile_body(typename CxT<T>::type* __restrict__ amp,
                                           const TilePass* __restrict__ pass,
                                           const TileSeg* __restrict__ segs,
                                           const TileOp* __restrict__ ops) {
   using C = typename CxT<T>::type;
+  using Off = std::conditional_t<LANE32, uint32_t, uint64_t>;
   constexpr int R = 1 << RB;
   extern __shared__ double lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
@@ -47,53 +58,74 @@ __device__ __forceinline__ void tile_body(typename CxT<T>::type* __restrict__ am
     tix = tb ? (__builtin_bitreverse32(tix) >> (32u - tb)) : 0u;
   }
   const uint64_t base = tile_base(pass, tix);
-  // HBM transfers use the I/O layout: registers select the top RB tile bits
-  // and consecutive threads take consecutive low tile bits, so a wave's
-  // accesses are contiguous runs of the lowest (always tile) qubits.
+  const int W = pass->L - RB;
+  const int lane_bits = W < 6 ? W : 6;
+  const uint32_t lane = tid & 63u;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  Off lane_el = 0;
+  for (int b = 0; b < lane_bits; ++b)
+    if (lane >> b & 1) lane_el |= Off(1) << pass->q[b];
+  const Off lane_off = lane_el * Off(sizeof(C));
+  uint64_t wave_el = base;
+  for (int b = 6; b < W; ++b)
+    if (wave >> (b - 6) & 1) wave_el |= uint64_t(1) << pass->q[b];
+  // byte step of each register bit (uniform)
+  uint64_t rstep[RB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i) rstep[i] = uint64_t(sizeof(C)) << pass->q[W + i];
   C a[R];
-  if constexpr (BOFF32) {
-    const uint32_t boff = io_thread_boff<C, RB>(pass, tid);
-    uint64_t roff[R];
-    io_reg_offsets<C, RB>(pass, roff);
-    const char* tile = reinterpret_cast<const char*>(amp + base);
+  {
+    const char* wp = reinterpret_cast<const char*>(amp) + wave_el * sizeof(C);
 #pragma unroll
-    for (int j = 0; j < R; ++j)
-      a[j] = load_at(amp, raw_rsrc<C>(tile + roff[j]), boff);
-    tile_apply<T, RB>(a, lds, pass, segs, ops, base, tid, true);
+    for (int j = 0; j < R; ++j) {
+      uint64_t ro = 0;
 #pragma unroll
-    for (int j = 0; j < R; ++j) store_at(raw_rsrc<C>(tile + roff[j]), boff, a[j]);
-  } else {
-    uint64_t gthr, greg[RB];
-    io_offsets<RB>(pass, base, tid, &gthr, greg);
+      for (int i = 0; i < RB; ++i)
+        if (j >> i & 1) ro += rstep[i];
+      a[j] = *reinterpret_cast<const C*>(wp + ro + lane_off);
+    }
+  }
+  tile_apply<T, RB>(a, lds, pass, segs, ops, base, tid, true);
+  // The store addresses are formed again from the few values they derive
+  // from (opaque to the compiler), so that the sixteen register addresses
+  // are not held in scalar registers across the op loop.
+  asm volatile("" : "+s"(wave_el));
 #pragma unroll
-    for (int j = 0; j < R; ++j) a[j] = amp[io_addr<RB>(gthr, greg, j)];
-    tile_apply<T, RB>(a, lds, pass, segs, ops, base, tid, true);
+  for (int i = 0; i < RB; ++i) asm volatile("" : "+s"(rstep[i]));
+  {
+    char* wp = reinterpret_cast<char*>(amp) + wave_el * sizeof(C);
 #pragma unroll
-    for (int j = 0; j < R; ++j) amp[io_addr<RB>(gthr, greg, j)] = a[j];
+    for (int j = 0; j < R; ++j) {
+      uint64_t ro = 0;
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+        if (j >> i & 1) ro += rstep[i];
+      *reinterpret_cast<C*>(wp + ro + lane_off) = a[j];
+    }
   }
 }
 
-// complex64 with 16 registers per thread: capped at 128 VGPRs so that four
-// waves share each SIMD.
-template <bool BOFF32>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+// complex64 with 16 registers per thread: capped at 96 VGPRs so that five
+// waves share each SIMD (five 32 KiB tiles fill the CU's 160 KiB of LDS).
+template <bool LANE32>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5)))
     tile_kernel_c64_rb4(float2* __restrict__ amp,
                         const TilePass* __restrict__ pass,
                         const TileSeg* __restrict__ segs,
                         const TileOp* __restrict__ ops) {
-  tile_body<float, 4, BOFF32>(amp, pass, segs, ops);
+  tile_body<float, 4, LANE32>(amp, pass, segs, ops);
 }
 
-template <typename T, int RB, bool BOFF32>
+template <typename T, int RB, bool LANE32>
 __global__ void __launch_bounds__(512)
     tile_kernel(typename CxT<T>::type* __restrict__ amp,
                 const TilePass* __restrict__ pass,
                 const TileSeg* __restrict__ segs,
                 const TileOp* __restrict__ ops) {
-  tile_body<T, RB, BOFF32>(amp, pass, segs, ops);
+  tile_body<T, RB, LANE32>(amp, pass, segs, ops);
 }
 
-// Kernel variants: 0 = 64-bit addressing, 1 = 32-bit offsets.
+// Kernel variants: 0 = 64-bit lane offsets, 1 = 32-bit lane offsets.
 template <typename T, int RB, int V>
 static const void* tile_fn() {
   if constexpr (sizeof(T) == 4 && RB == 4)
@@ -108,14 +140,16 @@ static hipError_t tile_launch(void* amp, int n, int L, const TilePass* pass,
                               hipStream_t stream) {
   using C = typename CxT<T>::type;
   const size_t lds = size_t(sizeof(C)) << L;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(tile_fn<T, RB, V>(),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  // set once per kernel function; callers on several threads (the server's
+  // scheduler and its clients) reach this together, hence call_once
+  static std::once_flag once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(once, [] {
+    attr_err = hipFuncSetAttribute(tile_fn<T, RB, V>(),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024);
+  });
+  if (attr_err != hipSuccess) return attr_err;
   const unsigned threads = 1u << (L - RB);
   const uint64_t tiles = uint64_t(1) << (n - L);
   if constexpr (sizeof(T) == 4 && RB == 4) {
@@ -128,10 +162,12 @@ static hipError_t tile_launch(void* amp, int n, int L, const TilePass* pass,
   return hipGetLastError();
 }
 
-hipError_t launch_tile(int prec, int rb, void* amp, int n, int L,
-                       int32_t flags, const TilePass* pass, const TileSeg* segs,
-                       const TileOp* ops, hipStream_t stream) {
-  const bool boff32 = (flags & kPassBoff32) != 0;
+hipError_t launch_tile(int prec, int rb, void* amp, int n,
+                       const TilePass& host_pass, const TilePass* pass,
+                       const TileSeg* segs, const TileOp* ops,
+                       hipStream_t stream) {
+  const int L = host_pass.L;
+  const bool boff32 = (host_pass.flags & kPassLane32) != 0;
   if (L - rb < 0 || L - rb > 9 || L > kMaxTileBits || n - L > 31)
     return hipErrorInvalidValue;
 #define QSV_T(T, RBV, V) return tile_launch<T, RBV, V>(amp, n, L, pass, segs, ops, stream)

@@ -321,6 +321,50 @@ static uint64_t angle_turns(double ang) {
   return (uint64_t(hi) << 32) + lo;  // wraps modulo 2^64
 }
 
+// The kernels' dispatch code of a finished op (see kCode* in program.h).
+// A dense op without a mux, or with one outside the tile, takes its matrix
+// by one bit of the tile's base index: the outer mux qubit, or bit 63,
+// which no index has (its second matrix is then a copy of the first).
+std::string set_op_code(TileOp* op) {
+  int32_t cls = 0;
+  op->arg = 0;
+  switch (op->kind) {
+    case kOpDense1:
+      if (op->mux == kMuxNone || op->mux < 0) {
+        cls = op->lctrl ? kCodeCtrl : kCodeUniform;
+        if (op->mux == kMuxNone) {
+          op->arg = 63;
+          std::memcpy(op->m2, op->m, sizeof op->m);
+          std::memcpy(op->mf2, op->mf, sizeof op->mf);
+        } else {
+          op->arg = -1 - op->mux;
+        }
+      } else if (op->lctrl == 0 && op->mux_reg >= 0) {
+        cls = kCodeRegMux;
+        op->arg = op->mux_reg;
+      } else {
+        cls = op->lctrl == 0 ? kCodeThreadMux : kCodeCtrlMux;
+        op->arg = op->mux;
+      }
+      if (op->reg < 0 || op->reg >= kMaxRegBits)
+        return "internal planner error: bad register index";
+      op->code = (cls << 3) | op->reg;
+      return "";
+    case kOpPhase:
+      op->code = kCodePhase << 3;
+      return "";
+    case kOpDiag:
+      op->code = kCodeDiag << 3;
+      op->arg = op->dk;
+      return "";
+    case kOpPhaseBlock:
+      op->code = kCodePhaseBlock << 3;
+      return "";
+    default:
+      return "internal planner error: unknown op kind";
+  }
+}
+
 std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
                            int RB, std::vector<TilePass>* tpasses,
                            std::vector<TileSeg>* tsegs,
@@ -330,12 +374,17 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
   tp.L = p.L;
   tp.nseg = int32_t(p.segs.size());
   tp.seg_begin = int32_t(tsegs->size());
-  // Thread bits of the I/O layout are tile bits 0..L-RB-1.  Their largest
-  // byte offset, below 16 * 2^(q[L-RB-1]+1) even for complex128, must stay
-  // below 2^31 for the buffer-resource (32-bit offset) addressing.
+  // Thread bits of the I/O layout are tile bits 0..L-RB-1; the lowest six
+  // of them index the lanes of a wave, the rest are uniform over a wave.
+  // The lane part of a byte offset is below 16 * 2^(q[lane bits - 1] + 1)
+  // even for complex128; where that fits 32 bits each access is a
+  // wave-uniform address plus a 32-bit lane offset.
   tp.flags = 0;
-  if ((p.L - RB <= 0) || (p.q[p.L - RB - 1] + 1 + 4 <= 31))
-    tp.flags |= kPassBoff32;
+  {
+    const int lane_bits = std::min(p.L - RB, 6);
+    if (lane_bits <= 0 || p.q[lane_bits - 1] + 1 + 4 <= 32)
+      tp.flags |= kPassLane32;
+  }
   // the tile is 2^(L - m) contiguous runs, m = its lowest contiguous qubits
   int m = 0;
   while (m < p.L && p.q[m] == m) ++m;
@@ -802,17 +851,21 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
     tsegs->push_back(ts);
   }
   // Locate each op's tile-local mux bit in its own segment's register bits
-  // (merges above may have changed an op's mux after its segment closed).
+  // (merges above may have changed an op's mux after its segment closed),
+  // then give every op its dispatch code.
   for (size_t si = 0; si < p.segs.size(); ++si) {
     const TileSeg& ts = (*tsegs)[tp.seg_begin + si];
     for (int oi = ts.op_begin; oi < ts.op_end; ++oi) {
       TileOp& op = (*tops)[oi];
       op.mux_reg = -1;
-      if (op.kind != kOpDense1 || op.mux == kMuxNone || op.mux < 0) continue;
-      for (int i = 0; i < RB; ++i)
-        if (ts.reg_bits[i] == op.mux) op.mux_reg = i;
-      if (op.mux_reg == op.reg)
-        return "internal planner error: mux bit equals the target bit";
+      if (op.kind == kOpDense1 && op.mux != kMuxNone && op.mux >= 0) {
+        for (int i = 0; i < RB; ++i)
+          if (ts.reg_bits[i] == op.mux) op.mux_reg = i;
+        if (op.mux_reg == op.reg)
+          return "internal planner error: mux bit equals the target bit";
+      }
+      std::string err = set_op_code(&op);
+      if (!err.empty()) return err;
     }
   }
   if (stats) stats->ops += tops->size() - size_t(op_base);

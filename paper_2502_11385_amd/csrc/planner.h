@@ -88,6 +88,10 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
                            std::vector<TileOp>* ops,
                            TileEmitStats* stats = nullptr);
 
+// Fill a finished tile op's dispatch code and argument (kernel header)
+// from its kind, mux and controls; returns an error text or "".
+std::string set_op_code(TileOp* op);
+
 // Algorithmic bytes of applying gate g as a plain per-gate kernel.
 uint64_t plain_gate_bytes(const HostGate& g, int n, int bytes_per_amp);
 

@@ -19,7 +19,39 @@ enum : int32_t {
   kOpPhaseBlock = 3  // a run of diagonal gates as one phase polynomial
 };
 
-// One gate inside a tile segment.
+// Dispatch classes of a tile op, precomputed by the planner (TileOp::code
+// = class << 3 | register index of the target).  The kernel reads an op's
+// header and both matrices in one batch of scalar loads and branches once.
+//  kCodeUniform:   2x2 matrix mf (m) on register bit `reg`, or mf2 (m2)
+//                  where bit `arg` of the tile's base index is 1 (an outer
+//                  mux qubit; arg = 63, a bit no index has, when there is
+//                  no mux).  The matrix is the same for the whole tile.
+//  kCodeRegMux:    mf where register bit `arg` of the pair's index is 0,
+//                  mf2 where it is 1 (fixed per register pair).
+//  kCodeThreadMux: mf or mf2 by tile-local bit `arg`, which a thread bit
+//                  holds (fixed per thread).
+//  kCodeCtrl:      as kCodeUniform, applied only where every tile-local
+//                  bit of lctrl is 1.
+//  kCodeCtrlMux:   mf or mf2 by tile-local bit `arg`, applied only where
+//                  every bit of lctrl is 1.
+//  kCodePhase:     multiply by mf[0..1] (m[0..1]) where every tile-local
+//                  bit of lctrl is 1.
+//  kCodeDiag:      diagonal table on arg (1 or 2) targets, see dbit0/1.
+//  kCodePhaseBlock: a PhaseBlock record `blob` bytes after the op.
+enum : int32_t {
+  kCodeUniform = 0,
+  kCodeRegMux = 1,
+  kCodeThreadMux = 2,
+  kCodeCtrl = 3,
+  kCodeCtrlMux = 4,
+  kCodePhase = 5,
+  kCodeDiag = 6,
+  kCodePhaseBlock = 7
+};
+
+// One gate inside a tile segment.  The first 32 bytes and the FP32 (mf,
+// mf2) or FP64 (m, m2) matrices are what the kernels read; the fields
+// after them describe the op for the host (planner, host emulation).
 //  kOpDense1: reg = index (0..RB-1) of the register bit holding the target;
 //             m = 2x2 complex matrix, row-major interleaved (see mux below).
 //  kOpDiag:   dk targets (1 or 2); dbit[j] >= 0 is the tile-local bit of
@@ -36,7 +68,20 @@ enum : int32_t {
 //  lctrl: controls inside the tile as a mask of tile-local bits.
 //  gctrl: controls outside the tile as a mask of global qubits.
 struct alignas(16) TileOp {
-  // header (the first 48 bytes, read by the kernels in one batch)
+  // kernel header (32 bytes)
+  int32_t code;   // class << 3 | reg (see kCode*)
+  int32_t arg;    // mux bit or outer mux qubit; target count for kCodeDiag
+  uint32_t lctrl;
+  int32_t blob;   // kOpPhaseBlock only
+  uint64_t gctrl;
+  int32_t dbit0;
+  int32_t dbit1;
+  // matrices
+  float mf[8];    // m rounded to FP32 (complex64 states)
+  float mf2[8];
+  double m[8];
+  double m2[8];
+  // host description
   int32_t kind;
   int32_t reg;
   // kOpDense1 only: the matrix may depend on one more qubit ("mux"):
@@ -47,18 +92,10 @@ struct alignas(16) TileOp {
   // holds it in the op's segment, or -1 when a thread bit holds it (then the
   // matrix is fixed per thread).  -1 for every other op.
   int32_t mux_reg;
-  uint32_t lctrl;
   int32_t dk;
-  int32_t dbit0;
-  int32_t dbit1;
-  uint64_t gctrl;
-  int32_t blob;  // kOpPhaseBlock only
-  int32_t pad_;
-  float mf[8];   // m rounded to FP32 (complex64 states)
-  float mf2[8];
-  double m[8];
-  double m2[8];
+  int32_t pad_[3];
 };
+static_assert(sizeof(TileOp) == 256, "tile ops are 256-byte records");
 
 constexpr int32_t kMuxNone = -1000;
 
@@ -105,14 +142,16 @@ struct alignas(16) TileSeg {
 };
 
 // TilePass flags.
-//  kPassBoff32: the I/O layout's thread byte offsets fit 32 bits, so the
-//               kernel may address HBM as buffer resource + 32-bit offset.
+//  kPassLane32: the lane part of the I/O layout's byte offsets (the lowest
+//               six thread bits spread over their tile qubits) fits 32
+//               bits, so each access is a wave-uniform 64-bit address plus
+//               one 32-bit per-lane offset.
 //  kPassSpread: work-group g takes tile bitreverse(g) instead of tile g, so
 //               that work-groups running at the same time touch far-apart
 //               parts of the state.  Used for tiles made of many short runs
 //               spaced by a large power of two, whose concurrent accesses
 //               otherwise crowd a few DRAM channels.
-constexpr int32_t kPassBoff32 = 1;
+constexpr int32_t kPassLane32 = 1;
 constexpr int32_t kPassSpread = 2;
 
 // One tile pass: 2^L amplitudes per tile, tile-local bit b is global qubit
@@ -121,7 +160,7 @@ struct alignas(16) TilePass {
   int32_t L;
   int32_t nseg;
   int32_t seg_begin;
-  int32_t flags;  // kPassBoff32 | kPassSpread
+  int32_t flags;  // kPassLane32 | kPassSpread
   int32_t q[16];
 };
 

@@ -19,36 +19,102 @@ __device__ __forceinline__ uint32_t lds_swz(uint32_t r) {
     return r ^ (((r >> 3) ^ (r >> 6) ^ (r >> 9)) & 7u);
 }
 
-template <int I, int R, bool CTRL, typename C, typename T>
-__device__ __forceinline__ void dense1_regs(C* a, T m0r, T m0i, T m1r, T m1i,
-                                            T m2r, T m2i, T m3r, T m3i,
-                                            uint32_t rt, const uint32_t* lr,
+// Pair update (x0, x1) <- M (x0, x1) for a 2x2 complex M = m[0..7]
+// (row-major, interleaved), in place: x0 = (a, b), x1 = (c, d).  Each
+// output first sums the three terms that do not read its own input (in
+// t0..t3, the four chains interleaved), then adds its own term into its own
+// register.  Written as one asm block per pair so that the amplitudes stay
+// in their registers through every switch arm of an op: compiled code
+// computed the new values into fresh registers and copied all sixteen
+// amplitudes back at the arms' join (32 moves per op, a fifth of its
+// instructions).  SM: the matrix is uniform, in scalar registers (each
+// instruction reads one of them); else it is in vector registers.
+#define QSV_PAIR_F32(MC)                                                      \
+  asm volatile(                                                               \
+      "v_mul_f32 %[t0], -%[m1], %[b]\n\t"                                     \
+      "v_mul_f32 %[t1], %[m1], %[a]\n\t"                                      \
+      "v_mul_f32 %[t2], %[m4], %[a]\n\t"                                      \
+      "v_mul_f32 %[t3], %[m4], %[b]\n\t"                                      \
+      "v_fmac_f32 %[t0], %[m2], %[c]\n\t"                                     \
+      "v_fmac_f32 %[t1], %[m2], %[d]\n\t"                                     \
+      "v_fma_f32 %[t2], -%[m5], %[b], %[t2]\n\t"                              \
+      "v_fmac_f32 %[t3], %[m5], %[a]\n\t"                                     \
+      "v_fma_f32 %[t0], -%[m3], %[d], %[t0]\n\t"                              \
+      "v_fmac_f32 %[t1], %[m3], %[c]\n\t"                                     \
+      "v_fma_f32 %[t2], -%[m7], %[d], %[t2]\n\t"                              \
+      "v_fmac_f32 %[t3], %[m7], %[c]\n\t"                                     \
+      "v_fma_f32 %[a], %[m0], %[a], %[t0]\n\t"                                \
+      "v_fma_f32 %[b], %[m0], %[b], %[t1]\n\t"                                \
+      "v_fma_f32 %[c], %[m6], %[c], %[t2]\n\t"                                \
+      "v_fma_f32 %[d], %[m6], %[d], %[t3]"                                     \
+      : [a] "+v"(x0.x), [b] "+v"(x0.y), [c] "+v"(x1.x), [d] "+v"(x1.y),     \
+        [t0] "=&v"(t0), [t1] "=&v"(t1), [t2] "=&v"(t2), [t3] "=&v"(t3)        \
+      : [m0] MC(m0r), [m1] MC(m0i), [m2] MC(m1r), [m3] MC(m1i),             \
+        [m4] MC(m2r), [m5] MC(m2i), [m6] MC(m3r), [m7] MC(m3i))
+#define QSV_PAIR_F64(MC)                                                      \
+  asm volatile(                                                               \
+      "v_mul_f64 %[t0], -%[m1], %[b]\n\t"                                     \
+      "v_mul_f64 %[t1], %[m1], %[a]\n\t"                                      \
+      "v_mul_f64 %[t2], %[m4], %[a]\n\t"                                      \
+      "v_mul_f64 %[t3], %[m4], %[b]\n\t"                                      \
+      "v_fma_f64 %[t0], %[m2], %[c], %[t0]\n\t"                               \
+      "v_fma_f64 %[t1], %[m2], %[d], %[t1]\n\t"                               \
+      "v_fma_f64 %[t2], -%[m5], %[b], %[t2]\n\t"                              \
+      "v_fma_f64 %[t3], %[m5], %[a], %[t3]\n\t"                               \
+      "v_fma_f64 %[t0], -%[m3], %[d], %[t0]\n\t"                              \
+      "v_fma_f64 %[t1], %[m3], %[c], %[t1]\n\t"                               \
+      "v_fma_f64 %[t2], -%[m7], %[d], %[t2]\n\t"                              \
+      "v_fma_f64 %[t3], %[m7], %[c], %[t3]\n\t"                               \
+      "v_fma_f64 %[a], %[m0], %[a], %[t0]\n\t"                                \
+      "v_fma_f64 %[b], %[m0], %[b], %[t1]\n\t"                                \
+      "v_fma_f64 %[c], %[m6], %[c], %[t2]\n\t"                                \
+      "v_fma_f64 %[d], %[m6], %[d], %[t3]"                                     \
+      : [a] "+v"(x0.x), [b] "+v"(x0.y), [c] "+v"(x1.x), [d] "+v"(x1.y),     \
+        [t0] "=&v"(t0), [t1] "=&v"(t1), [t2] "=&v"(t2), [t3] "=&v"(t3)        \
+      : [m0] MC(m0r), [m1] MC(m0i), [m2] MC(m1r), [m3] MC(m1i),             \
+        [m4] MC(m2r), [m5] MC(m2i), [m6] MC(m3r), [m7] MC(m3i))
+#define QSV_SREG(x) "s"(x)
+#define QSV_VREG(x) "v"(x)
+
+template <bool SM, typename C, typename T>
+__device__ __forceinline__ void pair2x2(C& x0, C& x1, T m0r, T m0i, T m1r,
+                                        T m1i, T m2r, T m2i, T m3r, T m3i) {
+  T t0, t1, t2, t3;
+  if constexpr (sizeof(T) == 4) {
+    if constexpr (SM) QSV_PAIR_F32(QSV_SREG);
+    else QSV_PAIR_F32(QSV_VREG);
+  } else {
+    if constexpr (SM) QSV_PAIR_F64(QSV_SREG);
+    else QSV_PAIR_F64(QSV_VREG);
+  }
+}
+
+template <int I, int R, bool CTRL, bool SM, typename C, typename T>
+__device__ __forceinline__ void dense1_regs(C* a, const T* m, uint32_t rt,
+                                            const uint32_t* lr,
                                             uint32_t lctrl) {
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     if (j & (1 << I)) continue;
     const int j1 = j | (1 << I);
-    const C x0 = a[j], x1 = a[j1];
-    C y0, y1;
-    y0.x = m0r * x0.x - m0i * x0.y + m1r * x1.x - m1i * x1.y;
-    y0.y = m0r * x0.y + m0i * x0.x + m1r * x1.y + m1i * x1.x;
-    y1.x = m2r * x0.x - m2i * x0.y + m3r * x1.x - m3i * x1.y;
-    y1.y = m2r * x0.y + m2i * x0.x + m3r * x1.y + m3i * x1.x;
     if constexpr (CTRL) {
+      C y0 = a[j], y1 = a[j1];
+      pair2x2<SM>(y0, y1, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7]);
       // rt and lr[j] have disjoint bits: test the thread part once
       const bool on = ((rt & lctrl) | (lr[j] & lctrl)) == lctrl;
-      a[j] = csel(on, y0, x0);
-      a[j1] = csel(on, y1, x1);
+      a[j] = csel(on, y0, a[j]);
+      a[j1] = csel(on, y1, a[j1]);
     } else {
-      a[j] = y0;
-      a[j1] = y1;
+      pair2x2<SM>(a[j], a[j1], m[0], m[1], m[2], m[3], m[4], m[5], m[6],
+                  m[7]);
     }
   }
 }
 
 // The same update with the matrix chosen per pair by tile-local bit mbit:
-// m0 where the bit is 0, m1 where it is 1 (mbit differs from the target).
-template <int I, int R, bool CTRL, typename C, typename T>
+// m0 where the bit is 0, m1 where it is 1 (mbit differs from the target),
+// applied only where every bit of lctrl is 1.
+template <int I, int R, typename C, typename T>
 __device__ __forceinline__ void dense1_mux_regs(C* a, const T* m0,
                                                 const T* m1, uint32_t rt,
                                                 const uint32_t* lr,
@@ -61,24 +127,15 @@ __device__ __forceinline__ void dense1_mux_regs(C* a, const T* m0,
     T m[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) m[e] = sel ? m1[e] : m0[e];
-    const C x0 = a[j], x1 = a[j1];
-    C y0, y1;
-    y0.x = m[0] * x0.x - m[1] * x0.y + m[2] * x1.x - m[3] * x1.y;
-    y0.y = m[0] * x0.y + m[1] * x0.x + m[2] * x1.y + m[3] * x1.x;
-    y1.x = m[4] * x0.x - m[5] * x0.y + m[6] * x1.x - m[7] * x1.y;
-    y1.y = m[4] * x0.y + m[5] * x0.x + m[6] * x1.y + m[7] * x1.x;
-    if constexpr (CTRL) {
-      const bool on = ((rt & lctrl) | (lr[j] & lctrl)) == lctrl;
-      a[j] = csel(on, y0, x0);
-      a[j1] = csel(on, y1, x1);
-    } else {
-      a[j] = y0;
-      a[j1] = y1;
-    }
+    C y0 = a[j], y1 = a[j1];
+    pair2x2<false>(y0, y1, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7]);
+    const bool on = ((rt & lctrl) | (lr[j] & lctrl)) == lctrl;
+    a[j] = csel(on, y0, a[j]);
+    a[j1] = csel(on, y1, a[j1]);
   }
 }
 
-template <int R, bool CTRL, typename C, typename T>
+template <int R, typename C, typename T>
 __device__ __forceinline__ void dense1_mux_dispatch(int reg, C* a, const T* m0,
                                                     const T* m1, uint32_t rt,
                                                     const uint32_t* lr,
@@ -86,7 +143,7 @@ __device__ __forceinline__ void dense1_mux_dispatch(int reg, C* a, const T* m0,
 #define QSV_D1M(I)                                                        \
   case I:                                                                 \
     if constexpr ((1 << I) < R) {                                         \
-      dense1_mux_regs<I, R, CTRL>(a, m0, m1, rt, lr, lctrl, mbit);        \
+      dense1_mux_regs<I, R>(a, m0, m1, rt, lr, lctrl, mbit);              \
       break;                                                              \
     } else {                                                              \
       __builtin_unreachable();                                            \
@@ -97,22 +154,20 @@ __device__ __forceinline__ void dense1_mux_dispatch(int reg, C* a, const T* m0,
     QSV_D1M(2)
     QSV_D1M(3)
     QSV_D1M(4)
-    QSV_D1M(5)
     default:
       __builtin_unreachable();  // the planner emits reg < RB only
   }
 #undef QSV_D1M
 }
 
-template <int R, bool CTRL, typename C, typename T>
+template <int R, bool CTRL, bool SM, typename C, typename T>
 __device__ __forceinline__ void dense1_dispatch(int reg, C* a, const T* m,
                                                 uint32_t rt, const uint32_t* lr,
                                                 uint32_t lctrl) {
 #define QSV_D1(I)                                                          \
   case I:                                                                  \
     if constexpr ((1 << I) < R) {                                          \
-      dense1_regs<I, R, CTRL>(a, m[0], m[1], m[2], m[3], m[4], m[5], m[6], \
-                              m[7], rt, lr, lctrl);                        \
+      dense1_regs<I, R, CTRL, SM>(a, m, rt, lr, lctrl);                    \
       break;                                                               \
     } else {                                                               \
       __builtin_unreachable();                                             \
@@ -123,7 +178,6 @@ __device__ __forceinline__ void dense1_dispatch(int reg, C* a, const T* m,
     QSV_D1(2)
     QSV_D1(3)
     QSV_D1(4)
-    QSV_D1(5)
     default:
       __builtin_unreachable();  // the planner emits reg < RB only
   }
@@ -140,14 +194,8 @@ __device__ __forceinline__ void dense1_muxreg_regs(C* a, const T* m0,
     if (j & (1 << I)) continue;
     const int j1 = j | (1 << I);
     const T* m = (j >> K & 1) ? m1 : m0;
-    const C x0 = a[j], x1 = a[j1];
-    C y0, y1;
-    y0.x = m[0] * x0.x - m[1] * x0.y + m[2] * x1.x - m[3] * x1.y;
-    y0.y = m[0] * x0.y + m[1] * x0.x + m[2] * x1.y + m[3] * x1.x;
-    y1.x = m[4] * x0.x - m[5] * x0.y + m[6] * x1.x - m[7] * x1.y;
-    y1.y = m[4] * x0.y + m[5] * x0.x + m[6] * x1.y + m[7] * x1.x;
-    a[j] = y0;
-    a[j1] = y1;
+    pair2x2<true>(a[j], a[j1], m[0], m[1], m[2], m[3], m[4], m[5], m[6],
+                  m[7]);
   }
 }
 
@@ -230,6 +278,15 @@ __device__ __forceinline__ void lds_reg_offsets(const Layout<RB>& lay,
     so[j] = so[j & (j - 1)] ^ basis[__builtin_ctz(j)];
 }
 
+// Work-group barrier for an exchange through LDS.  It waits for this wave's
+// LDS (and scalar) accesses only, not for its outstanding global memory
+// operations: a streaming tile pass keeps the next tile's prefetch and this
+// tile's stores in flight across the exchanges.  The asm is also a compiler
+// barrier, so no LDS access moves across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // Move the tile from layout `from` to layout `to` through LDS.
 // Threads with active == false (beyond the tile) only join the barriers.
 template <typename T, int RB, typename C>
@@ -249,7 +306,7 @@ __device__ __forceinline__ void relayout(C* a, C* lds, const Layout<RB>& from,
 #pragma unroll
     for (int j = 0; j < R; ++j) *reinterpret_cast<C*>(lb + (rf ^ so[j])) = a[j];
   }
-  __syncthreads();
+  lds_barrier();
   if (active) {
     lds_reg_offsets<T, RB>(to, so);
     const uint32_t rt =
@@ -257,7 +314,7 @@ __device__ __forceinline__ void relayout(C* a, C* lds, const Layout<RB>& from,
 #pragma unroll
     for (int j = 0; j < R; ++j) a[j] = *reinterpret_cast<const C*>(lb + (rt ^ so[j]));
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // e^{2 pi i t / 2^32} for a fixed-point fraction of a turn.  The top 24
@@ -287,17 +344,18 @@ __device__ __forceinline__ double2 turn_phase64(uint64_t t) {
 // bit, and the register table (terms on register bits only) the rest.
 template <typename T, int RB>
 __device__ __forceinline__ void phase_block(typename CxT<T>::type* a,
-                                            const PhaseBlock* pb, uint32_t rt,
-                                            uint64_t base) {
+                                            const PhaseBlock* pb_gen,
+                                            uint32_t rt, uint64_t base) {
   using C = typename CxT<T>::type;
   using U = typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type;
   constexpr int R = 1 << RB;
-  const PhaseTerm* t = reinterpret_cast<const PhaseTerm*>(pb + 1);
+  const cptr<PhaseBlock> pb = as_const(pb_gen);
+  cptr<PhaseTerm> t = as_const(reinterpret_cast<const PhaseTerm*>(pb_gen + 1));
   U acc[RB + 1];
   // A term's first 16 bytes (outer mask, thread mask, 32-bit turns) are
   // read as one vector, so that each term costs one scalar load round trip.
-  auto head = [](const PhaseTerm* p, uint64_t* gm, uint32_t* tm, U* w) {
-    const uint4 h = *reinterpret_cast<const uint4*>(p);
+  auto head = [](cptr<PhaseTerm> p, uint64_t* gm, uint32_t* tm, U* w) {
+    const u32x4 h = *(cptr<u32x4>)(p);
     *gm = uint64_t(h.x) | (uint64_t(h.y) << 32);
     *tm = h.z;
     if constexpr (sizeof(T) == 4) *w = U(h.w);
@@ -365,6 +423,67 @@ __device__ __forceinline__ void phase_block(typename CxT<T>::type* a,
   }
 }
 
+// The fields of one tile op that the kernels read: its 32-byte header and
+// both matrices (FP32 for complex64 states, FP64 for complex128), as raw
+// bit patterns, loaded in one batch of scalar loads.
+template <typename T>
+struct OpFields {
+  using B = std::conditional_t<sizeof(T) == 4, uint32_t, uint64_t>;
+  int32_t code, arg;
+  uint32_t lctrl;
+  int32_t blob;
+  uint64_t gctrl;
+  int32_t dbit0, dbit1;
+  B m0[8], m1[8];
+};
+
+template <typename T>
+__device__ __forceinline__ OpFields<T> load_op(const TileOp* op) {
+  OpFields<T> f;
+  const cptr<u32x4> h = as_const(reinterpret_cast<const u32x4*>(op));
+  const u32x4 h0 = h[0], h1 = h[1];
+  f.code = int32_t(h0.x);
+  f.arg = int32_t(h0.y);
+  f.lctrl = h0.z;
+  f.blob = int32_t(h0.w);
+  f.gctrl = uint64_t(h1.x) | (uint64_t(h1.y) << 32);
+  f.dbit0 = int32_t(h1.z);
+  f.dbit1 = int32_t(h1.w);
+  if constexpr (sizeof(T) == 4) {
+    const cptr<u32x4> mv = as_const(reinterpret_cast<const u32x4*>(op->mf));
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const u32x4 u = mv[i], v = mv[2 + i];
+      f.m0[4 * i] = u.x; f.m0[4 * i + 1] = u.y;
+      f.m0[4 * i + 2] = u.z; f.m0[4 * i + 3] = u.w;
+      f.m1[4 * i] = v.x; f.m1[4 * i + 1] = v.y;
+      f.m1[4 * i + 2] = v.z; f.m1[4 * i + 3] = v.w;
+    }
+  } else {
+    const cptr<u32x4> mv = as_const(reinterpret_cast<const u32x4*>(op->m));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const u32x4 u = mv[i], v = mv[4 + i];
+      f.m0[2 * i] = uint64_t(u.x) | (uint64_t(u.y) << 32);
+      f.m0[2 * i + 1] = uint64_t(u.z) | (uint64_t(u.w) << 32);
+      f.m1[2 * i] = uint64_t(v.x) | (uint64_t(v.y) << 32);
+      f.m1[2 * i + 1] = uint64_t(v.z) | (uint64_t(v.w) << 32);
+    }
+  }
+  return f;
+}
+
+// Every field of an op is live in scalar registers from here on: without
+// this the compiler sinks each load to its first use, and the op waits for
+// several dependent rounds of scalar loads instead of one.
+template <typename T>
+__device__ __forceinline__ void pin_op_fields(OpFields<T>& f) {
+  asm volatile("" : "+s"(f.code), "+s"(f.arg), "+s"(f.lctrl), "+s"(f.blob),
+                    "+s"(f.gctrl), "+s"(f.dbit0), "+s"(f.dbit1));
+#pragma unroll
+  for (int e = 0; e < 8; ++e) asm volatile("" : "+s"(f.m0[e]), "+s"(f.m1[e]));
+}
+
 // Apply every segment of one tile pass to the register tile `a`, which is
 // in the I/O layout on entry and is left in the I/O layout on exit.  `base`
 // is the tile's global index with all tile bits zero (outer controls and
@@ -377,111 +496,123 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
                                            const TileOp* ops, uint64_t base,
                                            uint32_t tid, bool active) {
   using C = typename CxT<T>::type;
+  using Bits = typename OpFields<T>::B;
   constexpr int R = 1 << RB;
-  const int W = pass->L - RB;
+  const cptr<TilePass> cp = as_const(pass);
+  const int W = cp->L - RB;
   Layout<RB> io;
 #pragma unroll
   for (int i = 0; i < RB; ++i) io.rb[i] = W + i;
   Layout<RB> cur = io;
-  const int nseg = pass->nseg;
-  const TileSeg* sp = segs + pass->seg_begin;
-  // complex64 amplitudes are carried as 64-bit values, so the copies where
-  // the ops' arms and the segments join move register pairs
-  using W64 = std::conditional_t<sizeof(T) == 4, uint64_t, C>;
-  W64 w[R];
-#pragma unroll
-  for (int j = 0; j < R; ++j) w[j] = __builtin_bit_cast(W64, a[j]);
+  const int nseg = cp->nseg;
+  const cptr<TileSeg> sp = as_const(segs) + cp->seg_begin;
   for (int s = 0; s < nseg; ++s) {
     Layout<RB> lay;
 #pragma unroll
     for (int i = 0; i < RB; ++i) lay.rb[i] = sp[s].reg_bits[i];
-    if (!same_layout(cur, lay)) {
-#pragma unroll
-      for (int j = 0; j < R; ++j) a[j] = __builtin_bit_cast(C, w[j]);
-      relayout<T, RB>(a, lds, cur, lay, tid, active);
-#pragma unroll
-      for (int j = 0; j < R; ++j) w[j] = __builtin_bit_cast(W64, a[j]);
-    }
+    if (!same_layout(cur, lay)) relayout<T, RB>(a, lds, cur, lay, tid, active);
     cur = lay;
     const uint32_t rt = thread_local_base(lay, tid);
-    uint32_t lr[R];
-#pragma unroll
-    for (int j = 0; j < R; ++j) lr[j] = reg_offset(lay, j);
-
-    for (int o = sp[s].op_begin; o < sp[s].op_end; ++o) {
-#pragma unroll
-      for (int j = 0; j < R; ++j) a[j] = __builtin_bit_cast(C, w[j]);
+    const int o_end = sp[s].op_end;
+    int o = sp[s].op_begin;
+    while (o < o_end) {
+      // Runs of control-free dense ops (the bulk of every circuit) go
+      // through a tight loop that branches only on the class and the
+      // target register, and whose every arm updates the amplitudes in
+      // place; controlled, phase and diagonal ops take the general path.
       const TileOp* op = ops + o;
-      // Read the header and both matrices before any branch, so that the
-      // scalar loads issue together and the op waits for them once (a
-      // variant that prefetched the next op's fields during this op was
-      // slower: the copies and the register pressure cost more than the
-      // latency it hid).
-      const int kind = op->kind;
-      const int oreg = op->reg;
-      const int mux = op->mux;
-      const int mreg = op->mux_reg;
-      const uint32_t lctrl = op->lctrl;
-      const uint64_t gctrl = op->gctrl;
+      // the header and both matrices, in one batch of scalar loads; the
+      // planner resolved every choice it could into the dispatch code
+      OpFields<T> f = load_op<T>(op);
+      pin_op_fields(f);
+      int cls = f.code >> 3;
+      if (cls <= kCodeThreadMux) {
+        for (;;) {
+          if ((base & f.gctrl) == f.gctrl) {  // else an outer control is 0
+            const int reg = f.code & 7;
+            if (cls == kCodeUniform) {
+              // one matrix for the whole tile, chosen by one bit of its
+              // base index (an outer mux qubit, or bit 63, which no index
+              // has); the choice is made on the bit patterns, so it stays
+              // scalar and the FMAs read the matrix from scalar registers
+              const bool second = ((base >> (f.arg & 63)) & 1) != 0;
+              T m[8];
+#pragma unroll
+              for (int e = 0; e < 8; ++e) {
+                Bits b = second ? f.m1[e] : f.m0[e];
+                asm volatile("" : "+s"(b));
+                m[e] = __builtin_bit_cast(T, b);
+              }
+              dense1_dispatch<R, false, true>(reg, a, m, rt, nullptr, 0u);
+            } else {
+              T m0[8], m1[8];
+#pragma unroll
+              for (int e = 0; e < 8; ++e) {
+                m0[e] = __builtin_bit_cast(T, f.m0[e]);
+                m1[e] = __builtin_bit_cast(T, f.m1[e]);
+              }
+              if (cls == kCodeRegMux) {
+                // mux bit in a register: the pairs' matrices are fixed
+                dense1_muxreg_dispatch<R>(reg, f.arg, a, m0, m1);
+              } else {
+                // mux bit in the thread index: one matrix per thread
+                const bool sel = ((rt >> f.arg) & 1u) != 0;
+                T m[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) m[e] = sel ? m1[e] : m0[e];
+                dense1_dispatch<R, false, false>(reg, a, m, rt, nullptr, 0u);
+              }
+            }
+          }
+          if (++o >= o_end) break;
+          f = load_op<T>(ops + o);
+          pin_op_fields(f);
+          cls = f.code >> 3;
+          if (cls > kCodeThreadMux) break;
+        }
+        continue;  // o is the next op of another class, or the end
+      }
+      ++o;
+      if ((base & f.gctrl) != f.gctrl) continue;  // an outer control is 0
+      const int reg = f.code & 7;
       T m0[8], m1[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        if constexpr (sizeof(T) == 4) {
-          m0[e] = op->mf[e];
-          m1[e] = op->mf2[e];
-        } else {
-          m0[e] = op->m[e];
-          m1[e] = op->m2[e];
-        }
+        m0[e] = __builtin_bit_cast(T, f.m0[e]);
+        m1[e] = __builtin_bit_cast(T, f.m1[e]);
       }
-      if ((base & gctrl) != gctrl) continue;  // an outer control bit is 0
-      if (kind == kOpDense1) {
-        // an outer mux qubit is fixed per tile: pick the matrix once
-        const bool second =
-            mux != kMuxNone && mux < 0 && ((base >> ((-1 - mux) & 63)) & 1);
-        T m[8], m2[8];
+      uint32_t lr[R];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          m[e] = second ? m1[e] : m0[e];
-          m2[e] = m1[e];
-        }
-        if (mux >= 0 && lctrl == 0 && mreg >= 0) {
-          // mux bit in a register: the pairs' matrices are fixed
-          dense1_muxreg_dispatch<R>(oreg, mreg, a, m, m2);
-        } else if (mux >= 0 && lctrl == 0) {
-          // mux bit in the thread index: one matrix per thread
-          const bool sel = ((rt >> mux) & 1u) != 0;
+      for (int j = 0; j < R; ++j) lr[j] = reg_offset(lay, j);
+      if (cls == kCodeCtrl) {
+        const bool second = ((base >> (f.arg & 63)) & 1) != 0;
+        T m[8];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) m[e] = sel ? m2[e] : m[e];
-          dense1_dispatch<R, false>(oreg, a, m, rt, lr, lctrl);
-        } else if (mux >= 0) {
-          dense1_mux_dispatch<R, true>(oreg, a, m, m2, rt, lr, lctrl, mux);
-        } else if (lctrl) {
-          dense1_dispatch<R, true>(oreg, a, m, rt, lr, lctrl);
-        } else {
-          dense1_dispatch<R, false>(oreg, a, m, rt, lr, lctrl);
-        }
-      } else if (kind == kOpPhaseBlock) {
+        for (int e = 0; e < 8; ++e) m[e] = second ? m1[e] : m0[e];
+        dense1_dispatch<R, true, false>(reg, a, m, rt, lr, f.lctrl);
+      } else if (cls == kCodeCtrlMux) {
+        dense1_mux_dispatch<R>(reg, a, m0, m1, rt, lr, f.lctrl, f.arg);
+      } else if (cls == kCodePhaseBlock) {
         phase_block<T, RB>(
             a,
             reinterpret_cast<const PhaseBlock*>(
-                reinterpret_cast<const char*>(op) + op->blob),
+                reinterpret_cast<const char*>(op) + f.blob),
             rt, base);
-      } else if (kind == kOpPhase) {
+      } else if (cls == kCodePhase) {
         C ph;
         ph.x = m0[0];
         ph.y = m0[1];
         // the index's thread and register parts have disjoint bits
-        const uint32_t tm = rt & lctrl;
+        const uint32_t tm = rt & f.lctrl;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-          const bool on = (tm | (lr[j] & lctrl)) == lctrl;
+          const bool on = (tm | (lr[j] & f.lctrl)) == f.lctrl;
           const C y = cmul(a[j], ph);
           a[j] = csel(on, y, a[j]);
         }
-      } else {  // kOpDiag
-        const int dk = op->dk;
-        const int d0 = op->dbit0, d1 = op->dbit1;
+      } else {  // kCodeDiag
+        const int dk = f.arg;
+        const int d0 = f.dbit0, d1 = f.dbit1;
         const uint32_t g0 =
             d0 < 0 ? uint32_t((base >> ((-1 - d0) & 63)) & 1) : 0u;
         const uint32_t g1 =
@@ -496,7 +627,7 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
         const uint32_t t0 = d0 >= 0 ? (rt >> (d0 & 31)) & 1u : g0;
         const uint32_t t1 =
             dk > 1 ? (d1 >= 0 ? (rt >> (d1 & 31)) & 1u : g1) : 0u;
-        const uint32_t tm = rt & lctrl;
+        const uint32_t tm = rt & f.lctrl;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
           const uint32_t b0 = d0 >= 0 ? t0 | ((lr[j] >> (d0 & 31)) & 1u) : g0;
@@ -504,18 +635,14 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
               dk > 1 ? (d1 >= 0 ? t1 | ((lr[j] >> (d1 & 31)) & 1u) : g1) : 0u;
           const C f01 = csel(b0 != 0, t[1], t[0]);
           const C f23 = csel(b0 != 0, t[3], t[2]);
-          const C f = csel(b1 != 0, f23, f01);
-          const bool on = (tm | (lr[j] & lctrl)) == lctrl;
-          const C y = cmul(a[j], f);
+          const C fv = csel(b1 != 0, f23, f01);
+          const bool on = (tm | (lr[j] & f.lctrl)) == f.lctrl;
+          const C y = cmul(a[j], fv);
           a[j] = csel(on, y, a[j]);
         }
       }
-#pragma unroll
-      for (int j = 0; j < R; ++j) w[j] = __builtin_bit_cast(W64, a[j]);
     }
   }
-#pragma unroll
-  for (int j = 0; j < R; ++j) a[j] = __builtin_bit_cast(C, w[j]);
   if (!same_layout(cur, io)) relayout<T, RB>(a, lds, cur, io, tid, active);
 }
 
