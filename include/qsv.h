@@ -69,18 +69,28 @@ typedef struct qsv_state_s* qsv_state;
 /* Allocate a 2^n_qubits state of precision prec on the current HIP device,
  * bound to hip_stream.  The library owns the 2^n * (8|16) bytes and frees
  * them in qsv_free.  The contents are undefined until initialised.
- * 1 <= n_qubits <= QSV_MAX_QUBITS. */
+ * 1 <= n_qubits <= QSV_MAX_QUBITS.  The state vector of full-circuit
+ * simulation in single or double precision (Section III.B), sized as in
+ * Table III (16 * 2^n bytes for complex128, half that for complex64); one
+ * GPU's HBM holds 34 complex64 or 33 complex128 qubits.  Errors:
+ * QSV_ERR_INVALID_ARG for n_qubits out of range or a NULL out,
+ * QSV_ERR_UNSUPPORTED for an unknown precision, QSV_ERR_OUT_OF_MEMORY when
+ * the device allocation fails (*out is then untouched). */
 qsv_status qsv_alloc(int32_t n_qubits, int32_t prec, void* hip_stream,
                      qsv_state* out);
 
 /* Bind a state to caller-owned device memory (e.g. a torch tensor's
  * storage) of at least 2^n * (8|16) bytes, 16-byte aligned.  The caller
- * keeps the memory alive until qsv_free; qsv_free does not release it. */
+ * keeps the memory alive until qsv_free; qsv_free does not release it.  The
+ * same state vector as qsv_alloc (Section III.B, Table III sizes) in memory
+ * the caller already holds.  Errors: QSV_ERR_INVALID_ARG for a NULL or
+ * misaligned pointer, too few bytes or n_qubits out of range,
+ * QSV_ERR_UNSUPPORTED for an unknown precision. */
 qsv_status qsv_wrap(int32_t n_qubits, int32_t prec, void* device_ptr,
                     size_t bytes, void* hip_stream, qsv_state* out);
 
 /* Release a state (and, for qsv_alloc states, its memory).  NULL is a
- * no-op.  Waits for the state's pending work first. */
+ * no-op.  Waits for the state's pending work first.  (Control call.) */
 qsv_status qsv_free(qsv_state s);
 
 /* Set the state to the computational basis state |index>: a[index] = 1,
@@ -144,14 +154,20 @@ typedef struct {
   int32_t reg_log2;
 } qsv_fuse_opts;
 
-/* Plan and apply a whole gate list.  The result equals applying the gates
- * one by one in list order (up to rounding): passes only regroup gates that
- * commute (disjoint qubits, or both diagonal).  Enqueued on the state's
- * stream. */
+/* Plan and apply a whole gate list: the transpile-time cache blocking of
+ * Section III.B (qubit and gate reordering onto the qubits of one chunk,
+ * here an LDS/register tile) followed by the passes it produces.  The
+ * result equals applying the gates one by one in list order (up to
+ * rounding): passes only regroup gates that commute (disjoint qubits, or
+ * both diagonal).  Enqueued on the state's stream.  Errors (nothing is
+ * enqueued): QSV_ERR_INVALID_ARG for a bad gate (qubit out of range,
+ * duplicate qubit, k outside 1..5, non-finite matrix) or option,
+ * QSV_ERR_OUT_OF_MEMORY when the program buffer cannot grow. */
 qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
                            const qsv_fuse_opts* opts);
 
-/* Statistics of the last qsv_apply_fused on this state:
+/* Statistics of the last qsv_apply_fused on this state (the passes of the
+ * cache-blocked plan, Section III.B):
  *   out[0] passes launched, out[1] gates, out[2] algorithmic HBM bytes
  *   (sum over passes of bytes read + written), out[3] tile passes,
  *   out[4] plain passes, out[5] fused passes, out[6] tile segments,
@@ -161,8 +177,9 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
  *   n_out <= 11 entries. */
 qsv_status qsv_last_plan_stats(qsv_state s, uint64_t* out, int32_t n_out);
 
-/* Per-pass timing.  While enabled (enable != 0), qsv_apply_fused records
- * a HIP event pair around every pass it launches, on the state's stream.
+/* Per-pass timing of the passes of Section III.B's cache-blocked plan.
+ * While enabled (enable != 0), qsv_apply_fused records a HIP event pair
+ * around every pass it launches, on the state's stream.
  * qsv_pass_times waits for the last qsv_apply_fused to finish and writes,
  * for its first min(cap, passes) passes, the kernel time in milliseconds
  * (ms_out) and the pass kind (kinds_out: 1 plain, 2 tile, 3 fused; may be
@@ -171,7 +188,8 @@ qsv_status qsv_set_profiling(qsv_state s, int32_t enable);
 qsv_status qsv_pass_times(qsv_state s, float* ms_out, int32_t* kinds_out,
                           int32_t cap, int32_t* count);
 
-/* Host-only planner dry run (no device work; usable without a GPU).
+/* Host-only planner dry run of the cache blocking of Section III.B (no
+ * device work; usable without a GPU).
  * For n_qubits and precision prec, writes for each gate g:
  *   gate_pass[g]  : index of the pass that applies g
  *   gate_order[j] : the j-th gate applied (a permutation of 0..n_gates-1)
@@ -197,7 +215,8 @@ qsv_status qsv_plan_program_stats(const qsv_circuit* circ, int32_t n_qubits,
                                   uint64_t* out, int32_t n_out);
 
 /* Testing aid (host only, no device work): plan the circuit with the
- * tiled strategy for n_qubits <= 16, build the exact device program the
+ * tiled strategy (Section III.B's cache blocking) for n_qubits <= 16,
+ * build the exact device program the
  * tile kernel would run (passes, register segments, folded and merged
  * ops) and execute it on the host in complex128 on `state` (2^n
  * interleaved re/im doubles, updated in place).  Lets the planner's
@@ -212,9 +231,10 @@ qsv_status qsv_debug_emulate_tiled(const qsv_circuit* circ, int32_t n_qubits,
 qsv_status qsv_gate_matrix(const char* name, const double* params,
                            int32_t n_params, double* out, int32_t* k_out);
 
-/* qsv_gate_matrix for `count` gates of one name: params holds count x
- * n_params values (gate i uses params[i*n_params ...]); out receives count
- * consecutive 2x2 matrices (8 doubles each). */
+/* qsv_gate_matrix for `count` gates of one name (the u1/u3 gates of
+ * Section III.B's example, in bulk): params holds count x n_params values
+ * (gate i uses params[i*n_params ...]); out receives count consecutive 2x2
+ * matrices (8 doubles each). */
 qsv_status qsv_gate_matrices(const char* name, const double* params,
                              int32_t n_params, size_t count, double* out);
 
@@ -227,11 +247,18 @@ qsv_status qsv_gate_matrices(const char* name, const double* params,
 qsv_status qsv_probabilities(qsv_state s, void* out_dev, int32_t out_fp64);
 
 /* Sum of p_i in FP64 with Neumaier compensation in a fixed-order tree
- * (bitwise reproducible for a given state).  Waits for the stream. */
+ * (bitwise reproducible for a given state).  The total of the probability
+ * vector the evaluator returns (Section IV.A), which the Verifier's error
+ * margin presupposes to be one; reported rather than assumed, since
+ * rounding moves it.  Waits for the stream; errors: QSV_ERR_INVALID_ARG for
+ * a NULL state or out, QSV_ERR_DEVICE for a failed state. */
 qsv_status qsv_norm(qsv_state s, double* out);
 
 /* Divide every amplitude by sqrt(norm); returns the norm before scaling in
- * *norm_out (may be NULL).  Waits for the stream. */
+ * *norm_out (may be NULL).  Restores a probability vector summing to one
+ * (Section IV.A) after rounding drift; optional, never implicit.  Waits
+ * for the stream; errors: QSV_ERR_INVALID_ARG for a NULL state or a zero
+ * norm, QSV_ERR_DEVICE for a failed state. */
 qsv_status qsv_renormalize(qsv_state s, double* norm_out);
 
 /* Marginal distribution of the specified qubits (the Builder's
@@ -275,7 +302,9 @@ qsv_status qsv_permute_qubits(qsv_state s, const int32_t* perm);
 qsv_status qsv_top_k(qsv_state s, uint32_t k, uint64_t* idx_out,
                      double* p_out);
 
-/* Expectation values <psi|P_t|psi> of n_terms Pauli strings (host arrays):
+/* Expectation values <psi|P_t|psi> of n_terms Pauli strings, the X/Y/Z
+ * observables whose eigenbases the cut identity uses (Section III.A,
+ * eq 3.1), as an output beside the probability vector (host arrays):
  * x_masks[t] has bit q set where P_t acts on qubit q with X or Y, z_masks[t]
  * where it acts with Z or Y (Y = i X Z).  out[t] (host) is the real value
  * for the state as it is (not renormalised); sums are FP64 with Neumaier
@@ -312,11 +341,11 @@ typedef struct {
  *   tile_log2 : tile size for every variant wider than it (default 12 c64,
  *               11 c128); variants at most this wide run in one tile
  *   reg_log2  : amplitudes per thread, as log2 (4, or 5 for c64)
- *   grid      : work-groups of the persistent launch (default: as many as
+ *   grid      : work-groups of each phase launch (default: as many as
  *               stay resident, from the kernel's occupancy)
  *   autotune  : time (tile_log2, reg_log2) candidates at creation and keep
  *               the fastest
- *   use_graph : capture the launch in a hipGraph and replay it
+ *   use_graph : capture the phase launches in a hipGraph and replay it
  *   out_fp64  : probabilities as double (else float) */
 typedef struct {
   int32_t tile_log2;
@@ -329,32 +358,48 @@ typedef struct {
 
 typedef struct qsv_batch_s* qsv_batch;
 
-/* Plan count variants of precision prec for one persistent launch on
- * hip_stream: the variants' programs are uploaded once, the work-groups
- * take variants longest-first in a fixed order (each variant's result is
- * independent of the rest of the batch), and every variant's probability
- * vector is written to a ragged output.  Allocates the program and the
- * scratch slots of variants wider than one tile. */
+/* Plan count variants of precision prec (the subcircuit variants of
+ * Section III.A, which the evaluator runs independently, Section IV.A) for
+ * phase launches on hip_stream.  Every variant is planned into tile passes
+ * and the programs are uploaded once.  Phase p applies pass p of every
+ * variant that has one: the phase's tiles, over all those variants, are
+ * divided among the work-groups by their estimated cost (ops per tile), and
+ * a kernel boundary separates the phases.  A variant that fits one tile
+ * starts from |0...0> in registers and is done in phase 0; a wider one keeps
+ * its state in the batch's scratch buffer between phases.  Each tile is
+ * computed the same way wherever it runs, so a variant's probabilities do
+ * not depend on the rest of the batch.  Allocates the program and the
+ * scratch buffer.  Errors: QSV_ERR_INVALID_ARG for a bad variant (width,
+ * labels, gates a tile cannot hold) or option, QSV_ERR_UNSUPPORTED for an
+ * unknown precision, QSV_ERR_OUT_OF_MEMORY when an allocation fails. */
 qsv_status qsv_batch_create(const qsv_variant* vars, size_t count,
                             int32_t prec, const qsv_batch_opts* opts,
                             void* hip_stream, qsv_batch* out);
 
 /* Ragged output layout: variant i's 2^width probabilities occupy elements
- * [offsets[i], offsets[i+1]) of the output; offsets holds count + 1. */
+ * [offsets[i], offsets[i+1]) of the output; offsets holds count + 1.  The
+ * per-variant probability vectors the reconstruction consumes
+ * (Section III.A). */
 qsv_status qsv_batch_out_offsets(qsv_batch b, uint64_t* offsets);
 
-/* Enqueue the batch (one kernel launch, or one graph replay) writing all
- * probability vectors into out_dev (caller-owned device memory of
- * offsets[count] floats or doubles). */
+/* Enqueue the batch writing all probability vectors into out_dev
+ * (caller-owned device memory of offsets[count] floats or doubles): one
+ * kernel launch per phase, or, with use_graph, one replay of a hipGraph
+ * holding those launches (captured at the first call for this out_dev, and
+ * captured again when out_dev changes).  Asynchronous on the batch's
+ * stream; the evaluation of every variant of Section III.A / IV.A.
+ * Errors: QSV_ERR_INVALID_ARG for a NULL batch or buffer, QSV_ERR_DEVICE
+ * when a launch fails. */
 qsv_status qsv_batch_launch(qsv_batch b, void* out_dev);
 
 /* out[0] variants, out[1] tile passes, out[2] tiles processed, out[3] ops,
  * out[4] scratch bytes, out[5] tile_log2, out[6] reg_log2, out[7] grid,
  * out[8] variants run in one tile, out[9] amplitude updates (sum over
- * variants of 2^width x ops).  n_out <= 10. */
+ * variants of 2^width x ops).  n_out <= 10.  (Control call.) */
 qsv_status qsv_batch_stats(qsv_batch b, uint64_t* out, int32_t n_out);
 
-/* Release a batch (waits for its stream).  NULL is a no-op. */
+/* Release a batch (waits for its stream).  NULL is a no-op.  (Control
+ * call.) */
 qsv_status qsv_batch_free(qsv_batch b);
 
 /* --------------------------------------------------------------- serving */
@@ -412,10 +457,13 @@ typedef struct {
 
 typedef struct qsv_server_s* qsv_server;
 
-/* Create a server (no device work until the first request runs). */
+/* Create a server (no device work until the first request runs): the
+ * evaluator's memory-sized worker pool of Section IV.A as one scheduler.
+ * Errors: QSV_ERR_INVALID_ARG for bad options or a NULL out. */
 qsv_status qsv_server_create(const qsv_server_opts* opts, qsv_server* out);
 
-/* Validate and enqueue a request (inputs are copied); returns its ticket.
+/* Validate and enqueue a request (a circuit for the evaluator, Section IV.A;
+ * inputs are copied); returns its ticket.
  * QSV_ERR_BUDGET if the request alone exceeds the budget.  The pinned host
  * buffer for its result is taken when the request is admitted to the
  * device; if that allocation fails the request completes with
@@ -423,21 +471,25 @@ qsv_status qsv_server_create(const qsv_server_opts* opts, qsv_server* out);
 qsv_status qsv_server_submit(qsv_server s, const qsv_request* req,
                              uint64_t* ticket);
 
-/* Block until the ticket's request has finished and describe its result. */
+/* Block until the ticket's request has finished and describe its result
+ * (the probability vector or shots of Sections III.A / IV.A).  Errors:
+ * QSV_ERR_INVALID_ARG for an unknown ticket; the request's own status is
+ * in out->status. */
 qsv_status qsv_server_wait(qsv_server s, uint64_t ticket, qsv_result* out);
 
-/* Free the ticket's result buffers. */
+/* Free the ticket's result buffers.  (Control call.) */
 qsv_status qsv_server_release(qsv_server s, uint64_t ticket);
 
 /* out[0] submitted, out[1] completed, out[2] batch launches, out[3] single
  * launches, out[4] peak reserved bytes, out[5] most groups in flight at
- * once, out[6] rejected.  n_out <= 7. */
+ * once, out[6] rejected.  n_out <= 7.  (Control call.) */
 qsv_status qsv_server_stats(qsv_server s, uint64_t* out, int32_t n_out);
 
-/* Finish queued work, stop the scheduler and free everything. */
+/* Finish queued work, stop the scheduler and free everything.  (Control
+ * call.) */
 qsv_status qsv_server_destroy(qsv_server s);
 
-/* The library's steady clock, in seconds. */
+/* The library's steady clock, in seconds.  (Control call.) */
 double qsv_clock(void);
 
 /* ---------------------------------------------------- cut reconstruction */
@@ -472,7 +524,8 @@ typedef struct {
   const int32_t* cut_out;
 } qsv_cut_spec;
 
-/* Device workspace that qsv_cut_reconstruct needs for this problem.
+/* Device workspace that qsv_cut_reconstruct needs for this problem (the
+ * reconstruction of Section III.A).
  * Validates the specification (QSV_ERR_INVALID_ARG with a message). */
 qsv_status qsv_cut_workspace_bytes(const qsv_cut_spec* spec, uint64_t* bytes);
 
@@ -504,21 +557,27 @@ qsv_status qsv_cut_reconstruct(const qsv_cut_spec* spec, const void* probs_dev,
 /* ---------------------------------------------------- copies and control */
 
 /* Copy all amplitudes to / from host memory (2^n interleaved pairs of the
- * state's precision).  Used for tests and checkpoints.  Waits. */
+ * state's precision): the state-vector copy between device and host that
+ * the evaluator makes before converting to probabilities (Section IV.A);
+ * here for tests and checkpoints, since every output is computed on the
+ * device.  Waits.  Errors: QSV_ERR_INVALID_ARG for a NULL state or buffer,
+ * QSV_ERR_DEVICE for a failed copy or state. */
 qsv_status qsv_get_amplitudes(qsv_state s, void* host_out);
 qsv_status qsv_set_amplitudes(qsv_state s, const void* host_in);
 
-/* Device pointer, qubit count and precision of a state. */
+/* Device pointer, qubit count and precision of a state.  (Control call.) */
 qsv_status qsv_info(qsv_state s, void** device_ptr, int32_t* n_qubits,
                     int32_t* prec);
 
-/* Wait for the state's stream; reports deferred device errors. */
+/* Wait for the state's stream; reports deferred device errors.  (Control
+ * call.) */
 qsv_status qsv_sync(qsv_state s);
 
-/* Thread-local message of the last failing call ("" if none). */
+/* Thread-local message of the last failing call ("" if none).  (Control
+ * call.) */
 const char* qsv_last_error(void);
 
-/* Library version string. */
+/* Library version string.  (Control call.) */
 const char* qsv_version(void);
 
 #ifdef __cplusplus

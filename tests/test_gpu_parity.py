@@ -418,6 +418,8 @@ def test_round_trip_30q(prec):
     assert abs(marg[x >> (n - 10)] - 1.0) < tol
     low = s.marginal(list(range(10)))
     assert abs(low[x & 1023] - 1.0) < tol
+    mid = s.marginal(list(range(10, 20)))
+    assert abs(mid[(x >> 10) & 1023] - 1.0) < tol
     s.free()
 
 
@@ -441,8 +443,10 @@ def test_qft_closed_form_full_width(n, prec):
     ph = np.array([((x * int(r)) % (1 << n)) / (1 << n) for r in rev],
                   dtype=np.float64)
     want = np.exp(2j * math.pi * ph) / math.sqrt(1 << n)
-    tol = 1e-6 if prec == C64 else 1e-12
-    assert np.max(np.abs(got - want)) <= tol
+    # relative to the amplitudes' size 2^(-n/2) (7.6e-6 at 34 qubits)
+    tol = (1e-4 if prec == C64 else 1e-10) / math.sqrt(1 << n)
+    err = np.max(np.abs(got - want))
+    assert err <= tol, f"max |da| = {err:.3e}, bound {tol:.3e}"
     s.free()
     del buf
     torch.cuda.empty_cache()
