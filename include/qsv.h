@@ -166,6 +166,47 @@ typedef struct {
 qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
                            const qsv_fuse_opts* opts);
 
+/* Outputs computed with a circuit (qsv_apply_fused_outputs).  Each is
+ * optional:
+ *   probs_dev  : device, 2^n probabilities p_i = |a_i|^2 as float
+ *                (probs_fp64 = 0) or double, as qsv_probabilities writes
+ *   marg_m     : 0, or the marginal of marg_qubits[0..marg_m-1] (host,
+ *                distinct, 1 <= marg_m <= 20) into marg_out (host, 2^marg_m
+ *                doubles), as qsv_marginal
+ *   n_shots    : 0, or n_shots draws (<= 2^32) with shot_seed into
+ *                shots_out (host), as qsv_sample */
+typedef struct {
+  void* probs_dev;
+  int32_t probs_fp64;
+  int32_t marg_m;
+  const int32_t* marg_qubits;
+  double* marg_out;
+  uint64_t n_shots;
+  uint64_t shot_seed;
+  uint64_t* shots_out;
+} qsv_outputs;
+
+/* qsv_apply_fused followed by the requested outputs, with the reductions
+ * folded into the circuit's last pass when it is a tile pass: that pass
+ * writes the probabilities and, per tile, FP64 sums of p over the tile's
+ * amplitudes grouped by the marginal's qubits and by the sampler's
+ * 1024-amplitude blocks, and two small kernels add those partial sums over
+ * the tiles in increasing tile order, so no output reads the state again
+ * (the distribution of specified qubits of the Builder, Section IV.A, and
+ * the shots of Section III.A, streamed out of the last gate pass).  The
+ * results equal qsv_apply_fused + qsv_probabilities + qsv_marginal +
+ * qsv_sample up to the order of the FP64 sums (so a draw may differ only
+ * where its uniform falls within rounding of a CDF step); a given state
+ * and request always give the same bits.  Outputs the last pass cannot
+ * fold (a plain or fused last pass, a marginal spanning more than
+ * tile_log2 - reg_log2 tile qubits, n <= 10 for shots) run as the separate
+ * kernels.  The state keeps its final amplitudes.  Waits for the stream
+ * when a host output is requested.  Errors: those of qsv_apply_fused, and
+ * QSV_ERR_INVALID_ARG for a bad output request (nothing is enqueued). */
+qsv_status qsv_apply_fused_outputs(qsv_state s, const qsv_circuit* circ,
+                                   const qsv_fuse_opts* opts,
+                                   const qsv_outputs* outs);
+
 /* Statistics of the last qsv_apply_fused on this state (the passes of the
  * cache-blocked plan, Section III.B):
  *   out[0] passes launched, out[1] gates, out[2] algorithmic HBM bytes
@@ -173,8 +214,10 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
  *   out[4] plain passes, out[5] fused passes, out[6] tile segments,
  *   out[7] host planning time in nanoseconds, out[8] tile ops,
  *   out[9] phase blocks (runs of diagonal gates applied as one phase
- *   polynomial), out[10] diagonal gates inside phase blocks.
- *   n_out <= 11 entries. */
+ *   polynomial), out[10] diagonal gates inside phase blocks, out[11] the
+ *   outputs the last pass folded (qsv_apply_fused_outputs: bit 0
+ *   probabilities, bit 1 marginal, bit 2 shots).
+ *   n_out <= 12 entries. */
 qsv_status qsv_last_plan_stats(qsv_state s, uint64_t* out, int32_t n_out);
 
 /* Per-pass timing of the passes of Section III.B's cache-blocked plan.

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libqsv.so")
 
 SOURCES = ["api.cpp", "planner.cpp", "batch.cpp", "server.cpp", "cut.cpp",
            "k_outputs.hip", "k_permute.hip",
-           "k_gate.hip", "k_cut.hip",
+           "k_gate.hip", "k_cut.hip", "k_stream.hip",
            "k_tile.hip", "k_reduce.hip", "k_fused.hip", "k_batch.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

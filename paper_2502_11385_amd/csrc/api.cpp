@@ -39,7 +39,7 @@ struct qsv_state_s {
   // reduction scratch
   char* scratch = nullptr;
   size_t scratch_cap = 0;
-  uint64_t stats[11] = {0};
+  uint64_t stats[12] = {0};
   // per-pass timing
   bool profiling = false;
   std::vector<hipEvent_t> evs;
@@ -416,10 +416,68 @@ static qsv_status plan_for(const qsv_circuit* circ, int n, int prec,
   return QSV_OK;
 }
 
+// Outputs requested with qsv_apply_fused_outputs, checked and laid out in
+// the state's scratch buffer.  A key's tile-local mask and bit count refer
+// to the circuit's last tile pass; fold_* says which outputs that pass
+// computes (the others run as separate kernels after the passes).
+struct OutPlan {
+  const qsv_outputs* o = nullptr;
+  bool fold_probs = false, fold_marg = false, fold_shots = false;
+  int last_tile = -1;         // index into the tile passes
+  uint32_t km = 0, ks = 0;    // key masks (tile-local bits)
+  int kbm = 0, kbs = 0;
+  size_t off_mpart = 0, off_mout = 0, off_blocks = 0, off_shots = 0,
+         off_spart = 0, off_other = 0, total = 0;
+};
+
+static qsv_status check_outputs(qsv_state s, const qsv_outputs* o) {
+  if (!o) return QSV_OK;
+  if (o->probs_fp64 != 0 && o->probs_fp64 != 1)
+    return fail(QSV_ERR_INVALID_ARG, "probs_fp64 must be 0 or 1");
+  if (o->marg_m < 0 || o->marg_m > 20 || o->marg_m > s->n)
+    return fail(QSV_ERR_INVALID_ARG, "marg_m must be 0..min(20, n)");
+  if (o->marg_m) {
+    if (!o->marg_qubits || !o->marg_out)
+      return fail(QSV_ERR_INVALID_ARG, "null marginal argument");
+    uint64_t seen = 0;
+    for (int l = 0; l < o->marg_m; ++l) {
+      const int q = o->marg_qubits[l];
+      if (q < 0 || q >= s->n)
+        return fail(QSV_ERR_INVALID_ARG, "marginal qubit out of range");
+      if (seen >> q & 1)
+        return fail(QSV_ERR_INVALID_ARG, "duplicate marginal qubit");
+      seen |= uint64_t(1) << q;
+    }
+  }
+  if (o->n_shots > (uint64_t(1) << 32))
+    return fail(QSV_ERR_INVALID_ARG, "n_shots must be <= 2^32");
+  if (o->n_shots && !o->shots_out)
+    return fail(QSV_ERR_INVALID_ARG, "null shots output");
+  return QSV_OK;
+}
+
+static qsv_status apply_fused_impl(qsv_state s, const qsv_circuit* circ,
+                                   const qsv_fuse_opts* opts,
+                                   const qsv_outputs* outs);
+
 qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
                            const qsv_fuse_opts* opts) {
+  return apply_fused_impl(s, circ, opts, nullptr);
+}
+
+qsv_status qsv_apply_fused_outputs(qsv_state s, const qsv_circuit* circ,
+                                   const qsv_fuse_opts* opts,
+                                   const qsv_outputs* outs) {
+  if (!outs) return fail(QSV_ERR_INVALID_ARG, "null outputs");
+  return apply_fused_impl(s, circ, opts, outs);
+}
+
+static qsv_status apply_fused_impl(qsv_state s, const qsv_circuit* circ,
+                                   const qsv_fuse_opts* opts,
+                                   const qsv_outputs* outs) {
   qsv_status st = check_state(s);
   if (st != QSV_OK) return st;
+  if ((st = check_outputs(s, outs)) != QSV_OK) return st;
   const auto t0 = std::chrono::steady_clock::now();
   std::vector<HostGate> G;
   PlanOptions po;
@@ -494,6 +552,60 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
       fblocks.push_back(fb);
     }
   }
+  // Outputs: which ones the last tile pass folds (the last pass of the plan
+  // must be a tile pass; a key may span at most L - reg_log2 tile bits, so
+  // that each thread's registers fall in one group), and the scratch
+  // layout: per-tile partial sums, the marginal, the sampler's block sums
+  // and scan, the shots, and the scratch of unfolded reductions.
+  OutPlan op;
+  op.o = outs;
+  if (outs) {
+    const bool last_is_tile =
+        !plan.passes.empty() && plan.passes.back().kind == kPassTile;
+    op.last_tile = last_is_tile ? int(tpasses.size()) - 1 : -1;
+    const int L = last_is_tile ? plan.passes.back().L : 0;
+    const int RB = po.reg_log2;
+    if (last_is_tile) {
+      const Pass& lp = plan.passes.back();
+      op.fold_probs = outs->probs_dev != nullptr;
+      if (outs->marg_m) {
+        for (int l = 0; l < outs->marg_m; ++l)
+          for (int b = 0; b < L; ++b)
+            if (lp.q[b] == outs->marg_qubits[l]) op.km |= 1u << b;
+        op.kbm = __builtin_popcount(op.km);
+        op.fold_marg = op.kbm <= L - RB;
+      }
+      if (outs->n_shots && n > 10) {
+        for (int b = 0; b < L; ++b)
+          if (lp.q[b] >= 10) op.ks |= 1u << b;
+        op.kbs = __builtin_popcount(op.ks);
+        op.fold_shots = op.kbs <= L - RB;
+      }
+    }
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    size_t off = 0;
+    const uint64_t tiles = last_is_tile ? uint64_t(1) << (n - L) : 0;
+    op.off_mpart = off;
+    if (op.fold_marg) off = al(off + (tiles << op.kbm) * sizeof(double));
+    op.off_mout = off;
+    if (outs->marg_m) off = al(off + (sizeof(double) << outs->marg_m));
+    op.off_blocks = off;
+    if (outs->n_shots) off = al(off + sample_scratch_bytes(n, 0));
+    op.off_shots = off;
+    if (outs->n_shots) off = al(off + outs->n_shots * sizeof(uint64_t));
+    op.off_spart = off;
+    if (op.fold_shots) off = al(off + (tiles << op.kbs) * sizeof(double));
+    op.off_other = off;
+    size_t other = 0;
+    if (outs->probs_dev && !op.fold_probs)
+      other = std::max(other, norm_scratch_bytes(n));
+    if (outs->marg_m && !op.fold_marg)
+      other = std::max(other, marginal_scratch_bytes(n, outs->marg_m));
+    op.total = off + al(other);
+    if ((st = select_device(s)) != QSV_OK) return st;
+    if ((st = ensure_scratch(s, op.total)) != QSV_OK) return st;
+  }
+
   // Fused outputs follow the gate matrices in the FP64 region.
   const size_t gate_doubles = mats.size();
   for (auto& fb : fblocks) fb.u64_offset += int64_t(gate_doubles);
@@ -511,6 +623,41 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
   const size_t o_fg = put(buf, fgates.data(), fgates.size());
   const size_t o_m64 = put(buf, mats.data(), mats.size());
   const size_t o_m32 = put(buf, mats32.data(), mats32.size());
+  if (outs && op.last_tile >= 0 &&
+      (op.fold_probs || op.fold_marg || op.fold_shots)) {
+    // the last tile pass's output record, after everything else
+    const TilePass& lp = tpasses[size_t(op.last_tile)];
+    const int L = lp.L, RB = po.reg_log2, W = L - RB;
+    OutSpec os = {};
+    os.probs = op.fold_probs ? uint64_t(uintptr_t(outs->probs_dev)) : 0;
+    os.probs_fp64 = outs->probs_fp64;
+    auto add_key = [&](uint32_t K, int kb, size_t part_off) {
+      const int k = os.n_keys++;
+      os.part[k] = uint64_t(uintptr_t(s->scratch + part_off));
+      os.key_bits[k] = kb;
+      // position term of tile bit c in group-major order
+      auto term = [&](int c) -> uint32_t {
+        const uint32_t below = (1u << c) - 1;
+        return (K >> c & 1) ? 1u << (L - kb + __builtin_popcount(K & below))
+                            : 1u << __builtin_popcount(~K & below);
+      };
+      for (int b = 0; b < W; ++b) os.thr_pos[k][b] = term(b);
+      for (int j = 0; j < (1 << RB); ++j) {
+        uint32_t v = 0;
+        for (int i = 0; i < RB; ++i)
+          if (j >> i & 1) v += term(W + i);
+        os.reg_pos[k][j] = v;
+      }
+    };
+    if (op.fold_marg) add_key(op.km, op.kbm, op.off_mpart);
+    if (op.fold_shots) add_key(op.ks, op.kbs, op.off_spart);
+    const size_t o_os = put(buf, &os, 1);
+    const size_t o_lp = o_tp + size_t(op.last_tile) * sizeof(TilePass);
+    TilePass* hp = reinterpret_cast<TilePass*>(buf.data() + o_lp);
+    hp->flags |= kPassOutputs;
+    hp->out_spec = int32_t(o_os - o_lp);
+    tpasses[size_t(op.last_tile)].flags |= kPassOutputs;
+  }
   const auto t1 = std::chrono::steady_clock::now();
 
   if ((st = select_device(s)) != QSV_OK) return st;
@@ -591,6 +738,89 @@ qsv_status qsv_apply_fused(qsv_state s, const qsv_circuit* circ,
   s->stats[8] = est.ops;
   s->stats[9] = est.blocks;
   s->stats[10] = est.block_gates;
+  s->stats[11] = 0;
+  if (!outs) return QSV_OK;
+
+  // ---- outputs: finish the folded reductions, run the others
+  s->stats[11] = (op.fold_probs ? 1 : 0) | (op.fold_marg ? 2 : 0) |
+                 (op.fold_shots ? 4 : 0);
+  const Pass* lp = op.last_tile >= 0 ? &plan.passes.back() : nullptr;
+  // tile-index bit of each outer qubit of the last tile pass
+  int tbit[64];
+  if (lp) {
+    uint64_t tq = 0;
+    for (int b = 0; b < lp->L; ++b) tq |= uint64_t(1) << lp->q[b];
+    for (int q = 0, r = 0; q < n; ++q) tbit[q] = (tq >> q & 1) ? -1 : r++;
+  }
+  auto local_of = [&](int q) -> int {
+    for (int b = 0; b < lp->L; ++b)
+      if (lp->q[b] == q) return b;
+    return -1;
+  };
+  char* sc = s->scratch;
+  if (outs->probs_dev && !op.fold_probs)
+    QSV_HIP(s, launch_probs(s->prec, s->amp, n, outs->probs_dev,
+                            outs->probs_fp64,
+                            reinterpret_cast<double*>(sc + op.off_other),
+                            nullptr, s->stream));
+  const int m = outs->marg_m;
+  double* mout = reinterpret_cast<double*>(sc + op.off_mout);
+  if (m && op.fold_marg) {
+    MargTileArgs a = {};
+    a.m = m;
+    a.kb = op.kbm;
+    uint64_t used = 0;
+    for (int l = 0; l < m; ++l) {
+      const int q = outs->marg_qubits[l];
+      const int b = local_of(q);
+      a.gpos[l] = b >= 0 ? __builtin_popcount(op.km & ((1u << b) - 1)) : -1;
+      a.tpos[l] = b >= 0 ? -1 : tbit[q];
+      if (b < 0) used |= uint64_t(1) << tbit[q];
+    }
+    for (int q = 0; q < n; ++q)
+      if (tbit[q] >= 0 && !(used >> tbit[q] & 1))
+        a.free_pos[a.free_bits++] = tbit[q];
+    a.n_enum = uint64_t(1) << a.free_bits;
+    QSV_HIP(s, launch_marg_tiles(reinterpret_cast<double*>(sc + op.off_mpart),
+                                 a, mout, s->stream));
+  } else if (m) {
+    QSV_HIP(s, launch_marginal(s->prec, s->amp, n, outs->marg_qubits, m,
+                               reinterpret_cast<double*>(sc + op.off_other),
+                               mout, s->stream));
+  }
+  uint64_t* sout = reinterpret_cast<uint64_t*>(sc + op.off_shots);
+  if (outs->n_shots && op.fold_shots) {
+    BlockTileArgs a = {};
+    a.nblocks = uint64_t(1) << (n - 10);
+    a.kb = op.kbs;
+    a.nhi = n - 10;
+    for (int i = 0; i < a.nhi; ++i) {
+      const int q = 10 + i;
+      const int b = local_of(q);
+      a.hi_g[i] = b >= 0 ? __builtin_popcount(op.ks & ((1u << b) - 1)) : -1;
+      a.hi_t[i] = b >= 0 ? -1 : tbit[q];
+    }
+    for (int q = 0; q < 10; ++q)
+      if (tbit[q] >= 0) a.free_pos[a.free_bits++] = tbit[q];
+    double* P = reinterpret_cast<double*>(sc + op.off_blocks);
+    QSV_HIP(s, launch_blocks_tiles(reinterpret_cast<double*>(sc + op.off_spart),
+                                   a, P, s->stream));
+    QSV_HIP(s, launch_sample_from_blocks(s->prec, s->amp, n, outs->n_shots,
+                                         outs->shot_seed, P, sout,
+                                         s->stream));
+  } else if (outs->n_shots) {
+    QSV_HIP(s, launch_sample(s->prec, s->amp, n, outs->n_shots,
+                             outs->shot_seed, sc + op.off_blocks, sout,
+                             s->stream));
+  }
+  if (m)
+    QSV_HIP(s, hipMemcpyAsync(outs->marg_out, mout, sizeof(double) << m,
+                              hipMemcpyDeviceToHost, s->stream));
+  if (outs->n_shots)
+    QSV_HIP(s, hipMemcpyAsync(outs->shots_out, sout,
+                              outs->n_shots * sizeof(uint64_t),
+                              hipMemcpyDeviceToHost, s->stream));
+  if (m || outs->n_shots) QSV_HIP(s, hipStreamSynchronize(s->stream));
   return QSV_OK;
 }
 
@@ -623,7 +853,7 @@ qsv_status qsv_pass_times(qsv_state s, float* ms_out, int32_t* kinds_out,
 
 qsv_status qsv_last_plan_stats(qsv_state s, uint64_t* out, int32_t n_out) {
   if (!s) return fail(QSV_ERR_INVALID_ARG, "null state");
-  if (!out || n_out < 0 || n_out > 11)
+  if (!out || n_out < 0 || n_out > 12)
     return fail(QSV_ERR_INVALID_ARG, "bad stats buffer");
   for (int i = 0; i < n_out; ++i) out[i] = s->stats[i];
   return QSV_OK;

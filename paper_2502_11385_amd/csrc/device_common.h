@@ -165,6 +165,46 @@ hipError_t launch_pauli(int prec, const void* amp, int n, uint64_t xm,
 hipError_t launch_sample(int prec, const void* amp, int n, uint64_t shots,
                          uint64_t seed, void* scratch, uint64_t* out_dev,
                          hipStream_t stream);
+// The same draws when the scratch already holds the 2^(n-10) block sums
+// (n > 10): the scan and the per-shot search only.
+hipError_t launch_sample_from_blocks(int prec, const void* amp, int n,
+                                     uint64_t shots, uint64_t seed,
+                                     void* scratch, uint64_t* out_dev,
+                                     hipStream_t stream);
+
+// Reductions over the per-tile partial sums of a last tile pass with
+// outputs (k_stream.hip).  Marginal bin j (output bit l = qubit qubits[l]):
+// gpos[l] >= 0 is its bit in the group index (a tile qubit), else tpos[l]
+// its bit in the tile index; the tile index bits of the other outer qubits
+// (free_pos, ascending) are enumerated, n_enum = 2^free_bits values.
+struct MargTileArgs {
+  int32_t m;
+  int32_t kb;
+  int32_t free_bits;
+  int32_t pad;
+  uint64_t n_enum;
+  int32_t gpos[20];
+  int32_t tpos[20];
+  int32_t free_pos[34];
+};
+hipError_t launch_marg_tiles(const double* part, const MargTileArgs& args,
+                             double* out_dev, hipStream_t stream);
+// Sampler block b (global bits 10..n-1, nhi = n - 10 of them): bit i of b is
+// qubit 10 + i, in the group index at hi_g[i] >= 0 (a tile qubit) or the
+// tile index at hi_t[i]; the outer qubits below 10 (free_pos, tile index
+// bits, ascending) are enumerated.
+struct BlockTileArgs {
+  uint64_t nblocks;
+  int32_t kb;
+  int32_t nhi;
+  int32_t free_bits;
+  int32_t pad;
+  int32_t hi_g[34];
+  int32_t hi_t[34];
+  int32_t free_pos[10];
+};
+hipError_t launch_blocks_tiles(const double* part, const BlockTileArgs& args,
+                               double* P, hipStream_t stream);
 // The same draws from a stored probability vector (float or double).
 hipError_t launch_sample_probs(int fp64, const void* probs, int n,
                                uint64_t shots, uint64_t seed, void* scratch,

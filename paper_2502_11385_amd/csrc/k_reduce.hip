@@ -477,6 +477,34 @@ hipError_t launch_sample(int prec, const void* amp, int n, uint64_t shots,
   return hipGetLastError();
 }
 
+template <class Acc>
+static void sample_from_blocks(const void* src, int n, uint64_t shots,
+                               uint64_t seed, void* scratch, uint64_t* out_dev,
+                               hipStream_t stream) {
+  using In = typename Acc::in_t;
+  const In* a = static_cast<const In*>(src);
+  const uint64_t nb = uint64_t(1) << (n - kSampleBlockLog);
+  double* P = static_cast<double*>(scratch);
+  scan_inclusive(P, nb, P + nb, stream);
+  if (shots)
+    sample_kernel<Acc><<<unsigned((shots + 3) / 4), 256, 0, stream>>>(
+        a, kSampleBlockLog, nb, P, shots, seed, out_dev);
+}
+
+hipError_t launch_sample_from_blocks(int prec, const void* amp, int n,
+                                     uint64_t shots, uint64_t seed,
+                                     void* scratch, uint64_t* out_dev,
+                                     hipStream_t stream) {
+  if (n <= kSampleBlockLog) return hipErrorInvalidValue;
+  if (prec == 1)
+    sample_from_blocks<FromAmps<float>>(amp, n, shots, seed, scratch, out_dev,
+                                        stream);
+  else
+    sample_from_blocks<FromAmps<double>>(amp, n, shots, seed, scratch,
+                                         out_dev, stream);
+  return hipGetLastError();
+}
+
 hipError_t launch_sample_probs(int fp64, const void* probs, int n,
                                uint64_t shots, uint64_t seed, void* scratch,
                                uint64_t* out_dev, hipStream_t stream) {

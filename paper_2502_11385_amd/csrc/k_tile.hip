@@ -17,6 +17,7 @@
 // gate that the planner could move onto the chunk's qubits.
 #include <mutex>
 
+#include "reduce_core.h"
 #include "tile_core.h"
 
 namespace qsv {
@@ -30,6 +31,70 @@ __device__ __forceinline__ uint64_t tile_base(const TilePass* pass,
   const int L = cp->L;
   for (int b = 0; b < L; ++b) base = insert_zero64(base, cp->q[b]);
   return base;
+}
+
+// Outputs of the last tile pass (kPassOutputs): p = |a|^2 of the tile's
+// final amplitudes (in the I/O layout, register j of thread tid is tile
+// index tid | j << W), stored if requested, then for each key the FP64 sum
+// over each group of the tile, in a fixed order: p staged in LDS in
+// group-major order, each thread sums its 2^RB consecutive entries (all in
+// one group), a pairwise tree combines the threads of each group.
+// e_base: element index of register 0 of this lane; e_reg[j]: element
+// offset of register j.
+template <typename T, int RB>
+__device__ __forceinline__ void tile_outputs(
+    const typename CxT<T>::type* a, typename CxT<T>::type* lds,
+    const TilePass* pass, uint32_t tix, uint64_t e_base, const uint64_t* e_reg,
+    uint32_t tid) {
+  constexpr int R = 1 << RB;
+  const cptr<TilePass> cp = as_const(pass);
+  const OutSpec* osg = reinterpret_cast<const OutSpec*>(
+      reinterpret_cast<const char*>(pass) + cp->out_spec);
+  const cptr<OutSpec> os = as_const(osg);
+  const int L = cp->L;
+  const int W = L - RB;
+  double p[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) p[j] = prob_of(a[j]);
+  const uint64_t probs = os->probs;
+  if (probs) {
+    if (os->probs_fp64) {
+      double* pd = reinterpret_cast<double*>(probs);
+#pragma unroll
+      for (int j = 0; j < R; ++j) pd[e_base + e_reg[j]] = p[j];
+    } else {
+      float* pf = reinterpret_cast<float*>(probs);
+#pragma unroll
+      for (int j = 0; j < R; ++j) pf[e_base + e_reg[j]] = float(p[j]);
+    }
+  }
+  double* sh = reinterpret_cast<double*>(lds);
+  const int n_keys = os->n_keys;
+  for (int k = 0; k < n_keys; ++k) {
+    const int kb = os->key_bits[k];
+    uint32_t tpos = 0;
+    for (int b = 0; b < W; ++b)
+      if (tid >> b & 1) tpos += os->thr_pos[k][b];
+    lds_barrier();  // every earlier use of the LDS is over
+#pragma unroll
+    for (int j = 0; j < R; ++j) sh[tpos + os->reg_pos[k][j]] = p[j];
+    lds_barrier();
+    double sum = 0;
+#pragma unroll
+    for (int e = 0; e < R; ++e) sum += sh[tid * R + e];
+    lds_barrier();
+    sh[tid] = sum;
+    const int tg = L - kb - RB;  // log2 of the threads per group
+    for (int st = 0; st < tg; ++st) {
+      lds_barrier();
+      if ((tid & ((2u << st) - 1)) == 0) sh[tid] += sh[tid + (1u << st)];
+    }
+    lds_barrier();
+    if ((tid & ((1u << tg) - 1)) == 0) {
+      double* part = reinterpret_cast<double*>(os->part[k]);
+      part[(uint64_t(tix) << kb) + (tid >> tg)] = sh[tid];
+    }
+  }
 }
 
 // One tile per work-group (at most 512 threads, L - RB <= 9).  HBM
@@ -102,6 +167,19 @@ __device__ __forceinline__ void tile_body(typename CxT<T>::type* __restrict__ am
         if (j >> i & 1) ro += rstep[i];
       *reinterpret_cast<C*>(wp + ro + lane_off) = a[j];
     }
+  }
+  if (as_const(pass)->flags & kPassOutputs) {
+    uint64_t e_reg[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      uint64_t ro = 0;
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+        if (j >> i & 1) ro += rstep[i];
+      e_reg[j] = ro / sizeof(C);
+    }
+    tile_outputs<T, RB>(a, lds, pass, tix, wave_el + uint64_t(lane_el), e_reg,
+                        tid);
   }
 }
 

@@ -153,6 +153,34 @@ struct alignas(16) TileSeg {
 //               otherwise crowd a few DRAM channels.
 constexpr int32_t kPassLane32 = 1;
 constexpr int32_t kPassSpread = 2;
+//  kPassOutputs: the pass also reduces its final amplitudes (an OutSpec
+//               `out_spec` bytes after the TilePass record).
+constexpr int32_t kPassOutputs = 4;
+
+// Outputs folded into a circuit's last tile pass.  After its amplitudes are
+// stored, each tile writes p = |a|^2 (optional) and, for up to two keys, the
+// FP64 sums of p over the groups of its amplitudes that share the tile bits
+// of the key: group g of tile x gathers the tile indices t with
+// pext(t, key_mask) = g, and its sum goes to part[x * 2^key_bits + g].
+// Within a tile the sum runs in a fixed order (16 consecutive group members
+// per thread, then a pairwise tree over threads), so the partial sums, and
+// the fixed-order reductions over tiles that follow, are reproducible.
+// The kernel stages p in LDS in group-major order, tile index t at
+// position (pext(t, key_mask) << (L - key_bits)) | pext(t, ~key_mask); a
+// position is the sum of one term per set bit of t, given here per thread
+// bit (tile bits 0..W-1 of the I/O layout) and per register index (tile
+// bits W..L-1).  The host requires key_bits <= L - RB, so that each
+// thread's 2^RB consecutive positions belong to one group.
+struct alignas(16) OutSpec {
+  uint64_t probs;       // device address of the 2^n probabilities, 0: none
+  int32_t probs_fp64;   // 1: double, 0: float
+  int32_t n_keys;       // 0..2
+  uint64_t part[2];     // device addresses of each key's partial sums
+  int32_t key_bits[2];  // popcount of each key's tile-local mask
+  int32_t pad_[2];
+  uint32_t thr_pos[2][10];
+  uint32_t reg_pos[2][32];
+};
 
 // One tile pass: 2^L amplitudes per tile, tile-local bit b is global qubit
 // q[b] (ascending).  Tiles are the cosets of the other n - L qubits.
@@ -160,8 +188,10 @@ struct alignas(16) TilePass {
   int32_t L;
   int32_t nseg;
   int32_t seg_begin;
-  int32_t flags;  // kPassLane32 | kPassSpread
+  int32_t flags;  // kPassLane32 | kPassSpread | kPassOutputs | kPassOutputs
   int32_t q[16];
+  int32_t out_spec;  // kPassOutputs: byte offset from this record
+  int32_t pad_[3];
 };
 
 // One gate of a fused block, in the block's local qubit numbering

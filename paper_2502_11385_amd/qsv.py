@@ -41,7 +41,8 @@ MAX_QUBITS = 34
 
 EXPORTED = [
     "qsv_alloc", "qsv_wrap", "qsv_free", "qsv_init_basis", "qsv_apply_gate",
-    "qsv_apply_fused", "qsv_last_plan_stats", "qsv_plan_describe",
+    "qsv_apply_fused", "qsv_apply_fused_outputs", "qsv_last_plan_stats",
+    "qsv_plan_describe",
     "qsv_gate_matrix", "qsv_probabilities", "qsv_norm", "qsv_renormalize",
     "qsv_marginal", "qsv_sample", "qsv_get_amplitudes", "qsv_set_amplitudes",
     "qsv_info", "qsv_sync", "qsv_last_error", "qsv_version",
@@ -84,6 +85,15 @@ class qsv_variant(C.Structure):
                 ("n_outputs", C.c_int32),
                 ("output_qubits", C.POINTER(C.c_int32)),
                 ("output_bases", C.POINTER(C.c_int32))]
+
+
+class qsv_outputs(C.Structure):
+    _fields_ = [("probs_dev", C.c_void_p), ("probs_fp64", C.c_int32),
+                ("marg_m", C.c_int32),
+                ("marg_qubits", C.POINTER(C.c_int32)),
+                ("marg_out", C.POINTER(C.c_double)),
+                ("n_shots", C.c_uint64), ("shot_seed", C.c_uint64),
+                ("shots_out", C.POINTER(C.c_uint64))]
 
 
 class qsv_batch_opts(C.Structure):
@@ -136,6 +146,9 @@ _SIGS = {
     "qsv_init_basis": [_p, _u64],
     "qsv_apply_gate": [_p, _pi32, _i32, _pi32, _i32, _pd],
     "qsv_apply_fused": [_p, C.POINTER(qsv_circuit), C.POINTER(qsv_fuse_opts)],
+    "qsv_apply_fused_outputs": [_p, C.POINTER(qsv_circuit),
+                                C.POINTER(qsv_fuse_opts),
+                                C.POINTER(qsv_outputs)],
     "qsv_last_plan_stats": [_p, _pu64, _i32],
     "qsv_plan_describe": [C.POINTER(qsv_circuit), _i32, _i32,
                           C.POINTER(qsv_fuse_opts), _pi32, _pi32, _pi32,
@@ -430,12 +443,34 @@ class State:
         _check(_lib.qsv_apply_fused(self._h, C.byref(st),
                                     C.byref(opts) if opts is not None else None))
 
+    def apply_fused_outputs(self, circ: Circuit,
+                            opts: Optional[qsv_fuse_opts] = None,
+                            probs_ptr: int = 0, probs_fp64: bool = False,
+                            marg_qubits: Sequence[int] = (),
+                            shots: int = 0, seed: int = 0):
+        """apply_fused plus outputs folded into the last tile pass:
+        returns (marginal or None, samples or None)."""
+        st = circ.struct()
+        mq = np.ascontiguousarray(np.asarray(marg_qubits, dtype=np.int32))
+        m = len(mq)
+        marg = np.zeros(1 << m, np.float64) if m else None
+        smp = np.zeros(shots, np.uint64) if shots else None
+        o = qsv_outputs(probs_ptr or None, 1 if probs_fp64 else 0, m,
+                        _ptr(mq, C.c_int32) if m else None,
+                        _ptr(marg, C.c_double) if m else None,
+                        int(shots), int(seed),
+                        _ptr(smp, C.c_uint64) if shots else None)
+        _check(_lib.qsv_apply_fused_outputs(
+            self._h, C.byref(st), C.byref(opts) if opts is not None else None,
+            C.byref(o)))
+        return marg, smp
+
     def plan_stats(self) -> dict:
-        out = np.zeros(11, np.uint64)
-        _check(_lib.qsv_last_plan_stats(self._h, _ptr(out, C.c_uint64), 11))
+        out = np.zeros(12, np.uint64)
+        _check(_lib.qsv_last_plan_stats(self._h, _ptr(out, C.c_uint64), 12))
         keys = ("passes", "gates", "alg_bytes", "tile_passes", "plain_passes",
                 "fused_passes", "segments", "plan_ns", "tile_ops",
-                "phase_blocks", "block_gates")
+                "phase_blocks", "block_gates", "folded_outputs")
         return {k: int(v) for k, v in zip(keys, out)}
 
     def set_profiling(self, enable: bool):

@@ -19,6 +19,10 @@ def workers() -> int:
 
 
 def pool_map(fn, items, chunksize: int = 1):
+    """fn over items in spawned worker processes, one BLAS thread each (the
+    workers inherit the environment at spawn), results in item order."""
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
     ctx = mp.get_context("spawn")
     with ctx.Pool(workers()) as pool:
         return pool.map(fn, items, chunksize=chunksize)
