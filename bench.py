@@ -26,9 +26,15 @@ if ROOT not in sys.path:
 METRIC = ("gate-pass HBM GB/s (% of peak), 30q depth-40 time; "
           "batched circuits/s, p99")
 PEAK_HBM_GBPS = 8000.0
+# vector FMA issue rate of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# x 2.4 GHz, for FP32 without packed instructions and for FP64 alike
+CLOCK_HZ = 2.4e9
+PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * CLOCK_HZ / 1e12
 N_QUBITS, DEPTH, SEED = 30, 40, 30
 SHOTS, SAMPLE_SEED = 1_000_000, 1000003
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_kernel_30q_c64_traffic.json")
+COUNTER_FILE = os.path.join(ROOT, "profiles",
+                            "tile_kernel_30q_c64_sq_counters.json")
 # the sources the tile kernel is compiled from (kernel, core, records)
 TILE_SRC = [os.path.join(ROOT, "paper_2502_11385_amd", "csrc", f)
             for f in ("k_tile.hip", "tile_core.h", "device_common.h",
@@ -38,6 +44,11 @@ TILE_SRC = [os.path.join(ROOT, "paper_2502_11385_amd", "csrc", f)
 def _note(msg: str) -> None:
     """Progress on stderr (stdout carries only the JSON line)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _opts_dict(o) -> dict:
+    return {"tile_log2": o.tile_log2, "low_qubits": o.low_qubits,
+            "reg_log2": o.reg_log2}
 
 
 def _src_hash(paths) -> str:
@@ -133,28 +144,237 @@ def cpu_configs_leg(budget_s: float) -> dict:
     return out
 
 
-def _cpu_subprocess(flag: str, budget_s: float):
+def host_info() -> dict:
+    """The host the oracle runs on: logical CPUs, the cores this process may
+    use, the CPU model and the RAM."""
+    info = {"os_cpu_count": os.cpu_count()}
+    try:
+        info["nproc"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        info["nproc"] = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    info["cpu_model"] = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        with open("/proc/meminfo") as f:
+            for ln in f:
+                if ln.startswith("MemTotal"):
+                    info["ram_GB"] = round(int(ln.split()[1]) * 1024 / 1e9, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
+def _oracle_variant(v):
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    gates = (oracle.cut_prologue(v.cut_inputs) + list(v.gates) +
+             oracle.cut_epilogue(v.cut_outputs))
+    psi = oracle.simulate(v.width, gates)
+    np.abs(psi) ** 2
+    return time.perf_counter() - t0
+
+
+def cpu_pool_leg(budget_s: float) -> dict:
+    """The oracle on the cut-variant batch as the paper's evaluator runs it:
+    a process pool sized by its CPU rule, min(3/4 of RAM / RAM per worker,
+    jobs, 3/4 of the cores), each worker one thread, over a seeded sample of
+    one variant per worker.  Circuits per second = workers / mean time per
+    variant, the pool's throughput with perfect packing."""
+    import multiprocessing as mp
+    import numpy as np
+    from circuits import batch_variants
+    vs = batch_variants(BATCH_COUNT, seed=BATCH_SEED)
+    hi = host_info()
+    cores = hi.get("nproc") or os.cpu_count() or 1
+    ram = hi.get("ram_GB") or 8.0
+    need_gb = 2 * (16 << max(v.width for v in vs)) / 1e9 + 0.3
+    workers = max(1, min(int(0.75 * ram / need_gb), len(vs), int(0.75 * cores)))
+    rng = np.random.default_rng(BATCH_SEED + 2)
+    pick = rng.choice(len(vs), min(len(vs), workers), replace=False)
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        times = pool.map(_oracle_variant, [vs[int(i)] for i in pick],
+                         chunksize=1)
+    dt = time.perf_counter() - t0
+    mean = float(np.mean(times))
+    return {"circuits_per_s": workers / mean, "cores": workers,
+            "wall_circuits_per_s": len(pick) / dt,
+            "sample": (f"{len(pick)} variants drawn with seed "
+                       f"{BATCH_SEED + 2} from the {BATCH_COUNT} (seed "
+                       f"{BATCH_SEED}) on {workers} worker processes "
+                       f"(min(3/4 RAM / {need_gb:.2f} GB, jobs, 3/4 of "
+                       f"{cores} cores)), complex128, mean {mean:.2f} s per "
+                       f"variant, {dt:.1f} s wall")}
+
+
+def _oracle_task(task):
+    """One oracle job of the errors leg (run in a worker process): the
+    20-qubit states, one batch variant's probabilities, or one served
+    request's probabilities (and its shots with their uniforms)."""
+    import oracle
+    from circuits import batch_variants, layered_circuit, qft_style_circuit
+    key, what = task[0], task[1]
+    if what == "d40":
+        return key, oracle.simulate(20, layered_circuit(20, DEPTH, SEED))
+    if what == "qft":
+        x, gq = qft_style_circuit(20, 34)
+        return key, oracle.simulate(20, gq, init=x)
+    if what == "variant":
+        v = batch_variants(BATCH_COUNT, seed=BATCH_SEED)[task[2]]
+        return key, oracle.variant_probabilities(v)
+    w, d, seed, shots = task[2:]
+    p = oracle.probabilities(oracle.simulate(w, layered_circuit(w, d, seed)))
+    if not shots:
+        return key, (p, None, None)
+    return key, (p, oracle.sample(p, shots, seed),
+                 oracle.uniforms(seed, shots))
+
+
+def _far_draws(got, want, p, u, delta: float) -> int:
+    """Draws that differ from the oracle's by more than a CDF step within
+    delta of the draw's threshold."""
+    import numpy as np
+    c = np.cumsum(p)
+    t = u * c[-1]
+    far = 0
+    for j in np.nonzero(got != want)[0]:
+        lo, hi = sorted((int(got[j]), int(want[j])))
+        if np.min(np.abs(c[lo:hi] - t[j])) > delta:
+            far += 1
+    return far
+
+
+def errors_leg(folder: str) -> dict:
+    """Achieved errors against the oracle (complex128 NumPy) of GPU results
+    saved by the GPU process: max |da| per amplitude and total variation
+    (TV) per result, max |dp| per probability, and for shots the draws that
+    differ from the oracle's beyond rounding of a CDF step.  The oracle
+    jobs run in a process pool of one-thread workers."""
+    import multiprocessing as mp
+    import numpy as np
+    import oracle
+    from circuits import ghz_circuit, layered_circuit
+    z = np.load(os.path.join(folder, "gpu.npz"))
+    meta = json.load(open(os.path.join(folder, "meta.json")))
+    out = {}
+    tasks = [("d40", "d40"), ("qft", "qft")]
+    if "batch_idx" in z.files:
+        tasks += [(f"v{k}", "variant", int(i))
+                  for k, i in enumerate(z["batch_idx"])]
+    reqs = meta.get("serve") or []
+    tasks += [(f"r{k}", "request", r["w"], r["d"], r["seed"], r["shots"])
+              for k, r in enumerate(reqs)]
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    _note(f"errors: {len(tasks)} oracle jobs on {workers} processes")
+    res = {}
+    with mp.get_context("spawn").Pool(workers) as pool:
+        for key, val in pool.imap_unordered(_oracle_task, tasks):
+            res[key] = val
+            if len(res) % 10 == 0:
+                _note(f"errors: {len(res)} of {len(tasks)} oracle jobs done")
+
+    def amp_err(got, want):
+        got = got.astype(np.complex128)
+        return {"max_abs_da": float(np.max(np.abs(got - want))),
+                "tv": float(0.5 * np.sum(np.abs(np.abs(got) ** 2 -
+                                                np.abs(want) ** 2)))}
+
+    w20 = res["d40"]
+    for key in meta["depth40_20q"]:
+        out[f"depth40_20q_{key}"] = amp_err(z[f"d40_{key}"], w20)
+    for key in meta["qft20"]:
+        out[f"qft_style_20q_{key}"] = amp_err(z[f"qft_{key}"], res["qft"])
+    p12 = oracle.probabilities(oracle.simulate(12, layered_circuit(12, 20, 12)))
+    pg = oracle.probabilities(oracle.simulate(12, ghz_circuit(12)))
+    for key in meta["config1"]:
+        want = pg if key.startswith("ghz") else p12
+        got = z[f"c1_{key}"].astype(np.float64)
+        out[f"config1_{key}"] = {"max_abs_dp": float(np.max(np.abs(got - want))),
+                                 "tv": float(0.5 * np.sum(np.abs(got - want)))}
+    # outputs folded into the last tile pass of the 20-qubit instance
+    p20 = oracle.probabilities(w20)
+    mw = oracle.marginal(p20, 20, list(range(10, 20)))
+    out["streamed_20q_c64_marginal"] = {
+        "max_abs_dP": float(np.max(np.abs(z["str_marg"] - mw)))}
+    ns = int(meta["streamed_shots"])
+    ow = oracle.sample(p20, ns, SAMPLE_SEED)
+    out["streamed_20q_c64_shots"] = {
+        "shots": ns, "differ": int(np.count_nonzero(z["str_shots"] != ow)),
+        "differ_beyond_rounding": _far_draws(
+            z["str_shots"], ow, p20, oracle.uniforms(SAMPLE_SEED, ns), 2e-4)}
+    if "batch_idx" in z.files:
+        offs = z["batch_offs"]
+        worst = tv = 0.0
+        for k in range(len(z["batch_idx"])):
+            gv = z["batch_p"][int(offs[k]):int(offs[k + 1])].astype(np.float64)
+            wv = res[f"v{k}"]
+            worst = max(worst, float(np.max(np.abs(gv - wv))))
+            tv = max(tv, float(0.5 * np.sum(np.abs(gv - wv))))
+        out["batch_sample"] = {"variants": len(z["batch_idx"]),
+                               "of": BATCH_COUNT, "max_abs_dp": worst,
+                               "max_tv": tv}
+    if reqs:
+        worst = 0.0
+        far = differ = draws = 0
+        for k, r in enumerate(reqs):
+            p, smp, u = res[f"r{k}"]
+            got = z[f"srv_{k}"]
+            if not r["shots"]:
+                worst = max(worst, float(np.max(np.abs(
+                    got.astype(np.float64) - p))))
+                continue
+            draws += len(got)
+            differ += int(np.count_nonzero(got != smp))
+            far += _far_draws(got, smp, p, u,
+                              1e-9 if r["prec"] == "c128" else 2e-4)
+        out["serve_sample"] = {
+            "requests": len(reqs), "sampled": meta["serve_total"],
+            "prob_vectors_max_abs_dp": worst, "shots": draws,
+            "shots_differ": differ, "shots_differ_beyond_rounding": far}
+    return out
+
+
+def _cpu_subprocess(flag: str, budget_s):
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         env[k] = "1"
+    # stderr passes through, so the legs' progress lines show
     r = subprocess.run([sys.executable, os.path.abspath(__file__),
                         flag, str(budget_s)], env=env,
-                       capture_output=True, text=True, timeout=600)
+                       stdout=subprocess.PIPE, text=True, timeout=900)
     if r.returncode != 0:
-        return None, r.stderr[-300:]
+        return None, f"{flag} exited with status {r.returncode}"
     return json.loads(r.stdout.strip().splitlines()[-1]), None
 
 
-def run_cpu_baseline(budget_s: float, batch_budget_s: float) -> dict:
+def run_cpu_baseline(budget_s: float, batch_budget_s: float,
+                     errors_dir=None) -> dict:
     res, err = _cpu_subprocess("--cpu-leg", budget_s)
     if res is None:
         return {"value": None, "unit": "GB/s", "cores": 1, "kind": "oracle",
                 "sample": "failed: " + err}
+    res["host"] = host_info()
     if batch_budget_s > 0:
         bres, berr = _cpu_subprocess("--cpu-batch-leg", batch_budget_s)
         res["batch"] = bres if bres is not None else {"failed": berr}
+        pres, perr = _cpu_subprocess("--cpu-pool-leg", batch_budget_s)
+        res["batch_pool"] = pres if pres is not None else {"failed": perr}
     cres, cerr = _cpu_subprocess("--cpu-configs-leg", 6.0)
     res["configs"] = cres if cres is not None else {"failed": cerr}
+    if errors_dir:
+        eres, eerr = _cpu_subprocess("--errors-leg", errors_dir)
+        res["errors"] = eres if eres is not None else {"failed": eerr}
     return res
 
 
@@ -173,7 +393,9 @@ def small_leg(qsv, torch, np, reps: int = 200) -> dict:
     """The 12-qubit circuits (layered depth 20, seed 12; GHZ-12), each
     circuit a full call sequence (init, planned passes, FP64 probability
     vector into a device buffer) on one stream, repeated; microseconds per
-    circuit from the wall clock around `reps` back-to-back circuits."""
+    circuit from the wall clock around `reps` back-to-back circuits.  Both
+    precisions under the default plan, and complex128 under the plain
+    per-gate plan."""
     from circuits import ghz_circuit, layered_circuit
     n = 12
     res = {"workload": ("12-qubit layered random circuit (depth 20, 240 U3 + "
@@ -183,17 +405,21 @@ def small_leg(qsv, torch, np, reps: int = 200) -> dict:
     for cname, gates in (("layered12", layered_circuit(n, 20, 12)),
                          ("ghz12", ghz_circuit(n))):
         circ = qsv.Circuit.from_gates(gates)
-        for pname, prec in (("c64", qsv.QSV_C64), ("c128", qsv.QSV_C128)):
+        for pname, prec, strat in (("c64", qsv.QSV_C64, 0),
+                                   ("c128", qsv.QSV_C128, 0),
+                                   ("c128_plain", qsv.QSV_C128,
+                                    qsv.PLAN_PLAIN)):
             s = qsv.State(n, prec, stream=torch.cuda.current_stream())
+            o = qsv.fuse_opts(strategy=strat)
             for _ in range(5):
                 s.init_basis(0)
-                s.apply_fused(circ)
+                s.apply_fused(circ, o)
                 s.probabilities_into(probs.data_ptr(), True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(reps):
                 s.init_basis(0)
-                s.apply_fused(circ)
+                s.apply_fused(circ, o)
                 s.probabilities_into(probs.data_ptr(), True)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
@@ -205,6 +431,89 @@ def small_leg(qsv, torch, np, reps: int = 200) -> dict:
             s.free()
     del probs
     return res
+
+
+ERR_SHOTS = 100_000
+
+
+def errors_inputs(qsv, torch, np, saved: dict) -> None:
+    """GPU results the oracle subprocess compares (outside every timed
+    region): the 20-qubit depth-40 instance (seed 30) under each plan and
+    precision, the 20-qubit QFT-style instance (seed 34, 10 tail layers),
+    the 12-qubit configurations' probability vectors, and the folded
+    top-10 marginal and 10^5 shots of the 20-qubit instance."""
+    from circuits import ghz_circuit, layered_circuit, qft_style_circuit
+    meta = saved.setdefault("meta", {})
+    arr = saved.setdefault("arrays", {})
+    st = torch.cuda.current_stream()
+    c20 = qsv.Circuit.from_gates(layered_circuit(20, DEPTH, SEED))
+    meta["depth40_20q"] = []
+    for pname, prec in (("c64", qsv.QSV_C64), ("c128", qsv.QSV_C128)):
+        s = qsv.State(20, prec, stream=st)
+        for sname, strat in (("plain", qsv.PLAN_PLAIN),
+                             ("fused", qsv.PLAN_FUSED),
+                             ("tiled", qsv.PLAN_TILED)):
+            s.init_basis(0)
+            s.apply_fused(c20, qsv.fuse_opts(strategy=strat))
+            arr[f"d40_{sname}_{pname}"] = s.get()
+            meta["depth40_20q"].append(f"{sname}_{pname}")
+        if prec == qsv.QSV_C64:
+            p = torch.empty(1 << 20, dtype=torch.float32, device="cuda")
+            s.init_basis(0)
+            marg, smp = s.apply_fused_outputs(
+                c20, None, probs_ptr=p.data_ptr(), marg_qubits=range(10, 20),
+                shots=ERR_SHOTS, seed=SAMPLE_SEED)
+            arr["str_marg"] = marg
+            arr["str_shots"] = smp
+            meta["streamed_shots"] = ERR_SHOTS
+            del p
+        s.free()
+    x, gq = qft_style_circuit(20, 34)
+    cq = qsv.Circuit.from_gates(gq)
+    meta["qft20"] = []
+    for pname, prec in (("c64", qsv.QSV_C64), ("c128", qsv.QSV_C128)):
+        s = qsv.State(20, prec, stream=st)
+        s.init_basis(x)
+        s.apply_fused(cq)
+        arr[f"qft_{pname}"] = s.get()
+        meta["qft20"].append(pname)
+        s.free()
+    meta["config1"] = []
+    for cname, gates in (("layered12", layered_circuit(12, 20, 12)),
+                         ("ghz12", ghz_circuit(12))):
+        c = qsv.Circuit.from_gates(gates)
+        for key, prec, strat in (("c128_plain", qsv.QSV_C128, qsv.PLAN_PLAIN),
+                                 ("c128", qsv.QSV_C128, 0),
+                                 ("c64", qsv.QSV_C64, 0)):
+            s = qsv.State(12, prec, stream=st)
+            s.init_basis(0)
+            s.apply_fused(c, qsv.fuse_opts(strategy=strat))
+            arr[f"c1_{cname}_{key}"] = s.probabilities(
+                fp64=prec == qsv.QSV_C128).cpu().numpy()
+            meta["config1"].append(f"{cname}_{key}")
+            s.free()
+    torch.cuda.synchronize()
+
+
+def write_errors_inputs(np, saved: dict) -> str:
+    """Write the saved GPU results to a fresh temporary folder."""
+    import tempfile
+    d = tempfile.mkdtemp(prefix="qsv_bench_err_")
+    arr = dict(saved.get("arrays", {}))
+    meta = dict(saved.get("meta", {}))
+    for k in ("batch_idx", "batch_offs", "batch_p"):
+        if k in saved:
+            arr[k] = saved[k]
+    if saved.get("serve"):
+        meta["serve"] = [{k: v for k, v in r.items() if k != "data"}
+                         for r in saved["serve"]]
+        meta["serve_total"] = saved["serve_total"]
+        for i, r in enumerate(saved["serve"]):
+            arr[f"srv_{i}"] = r["data"]
+    np.savez(os.path.join(d, "gpu.npz"), **arr)
+    with open(os.path.join(d, "meta.json"), "w") as f:
+        json.dump(meta, f)
+    return d
 
 
 def cut_leg(qsv, torch, np, steps: int) -> dict:
@@ -256,18 +565,23 @@ def cut_leg(qsv, torch, np, steps: int) -> dict:
 
 
 def plans_leg(qsv, torch, np, circ, n: int) -> dict:
-    """The 30-qubit depth-40 circuit under each plan and both precisions:
+    """The 30-qubit depth-40 circuit under each plan and both precisions
+    (the tiled plan with the default and with autotuned tile parameters):
     passes, circuit time (sum of pass times, HIP events) and the mean
     algorithmic GB/s per pass."""
     res = {}
     for pname, prec in (("c64", qsv.QSV_C64), ("c128", qsv.QSV_C128)):
         s = qsv.State(n, prec, stream=torch.cuda.current_stream())
         s.set_profiling(True)
-        for sname, strat in (("plain", qsv.PLAN_PLAIN),
-                             ("fused", qsv.PLAN_FUSED),
-                             ("tiled", qsv.PLAN_TILED)):
+        s.init_basis(0)
+        tuned, _, _, _ = s.autotune(circ, qsv.fuse_opts(
+            strategy=qsv.PLAN_TILED))
+        for sname, o in (("plain", qsv.fuse_opts(strategy=qsv.PLAN_PLAIN)),
+                         ("fused", qsv.fuse_opts(strategy=qsv.PLAN_FUSED)),
+                         ("tiled", qsv.fuse_opts(strategy=qsv.PLAN_TILED)),
+                         ("tiled_autotuned", tuned)):
             s.init_basis(0)
-            s.apply_fused(circ, qsv.fuse_opts(strategy=strat))
+            s.apply_fused(circ, o)
             s.sync()
             ms, _ = s.pass_times()
             st = s.plan_stats()
@@ -276,6 +590,8 @@ def plans_leg(qsv, torch, np, circ, n: int) -> dict:
                 "passes": st["passes"], "circuit_ms": round(tot, 2),
                 "mean_pass_GBps": round(st["alg_bytes"] / (tot * 1e-3) / 1e9,
                                         1)}
+            if sname == "tiled_autotuned":
+                res[f"{sname}_{pname}"].update(_opts_dict(o))
         s.free()
         torch.cuda.empty_cache()
     return res
@@ -298,13 +614,15 @@ def wide_leg(qsv, torch, np) -> dict:
         x, gates = qft_style_circuit(n, seed)
         circ = qsv.Circuit.from_gates(gates)
         s = qsv.State(n, prec, stream=torch.cuda.current_stream())
+        s.init_basis(x)
+        best, bms, dms, _ = s.autotune(circ)
         s.set_profiling(True)
         tot = 0.0
         for _ in range(2):
             s.init_basis(x)
-            s.apply_fused(circ)
+            s.apply_fused(circ, best)
             s.sync()
-            ms, _ = s.pass_times()
+            ms, kinds = s.pass_times()
             tot = float(ms.sum())
         st = s.plan_stats()
         t0 = time.perf_counter()
@@ -312,10 +630,17 @@ def wide_leg(qsv, torch, np) -> dict:
         t1 = time.perf_counter()
         s.sample(SHOTS, SAMPLE_SEED)
         t2 = time.perf_counter()
+        tile_ms = float(ms[kinds == 2].sum()) if (kinds == 2).any() else 0.0
         res[f"{n}q_{pname}"] = {
             "gates": len(gates), "passes": st["passes"],
+            "tile_passes": st["tile_passes"], "tile_ops": st["tile_ops"],
             "circuit_ms": round(tot, 1),
+            "autotuned": dict(_opts_dict(best),
+                              tuner_circuit_ms=round(bms, 1),
+                              default_circuit_ms=round(dms, 1)),
             "mean_pass_GBps": round(st["alg_bytes"] / (tot * 1e-3) / 1e9, 1),
+            "tile_TFLOPs": round(st["tile_flops"] / (tile_ms * 1e-3) / 1e12,
+                                 2) if tile_ms else None,
             "marginal_ms": round((t1 - t0) * 1e3, 2),
             "samples_ms": round((t2 - t1) * 1e3, 2),
             "marginal_sum": float(np.sum(marg))}
@@ -324,11 +649,16 @@ def wide_leg(qsv, torch, np) -> dict:
     return res
 
 
-def batch_leg(qsv, torch, np, steps: int, per_circuit: bool) -> dict:
-    """4096 cut variants (widths 10..20, depths 10..60), complex64: one
-    persistent launch (autotuned, replayed from a hipGraph) against one
-    library call sequence per circuit (init, planned passes, probabilities)
-    on the whole GPU."""
+BATCH_CHECK_FRAC, BATCH_CHECK_SEED = 0.01, 4097
+
+
+def batch_leg(qsv, torch, np, steps: int, per_circuit: bool,
+              saved=None) -> dict:
+    """4096 cut variants (widths 10..20, depths 10..60), complex64: the
+    autotuned phase launches replayed from a hipGraph, against one library
+    call sequence per circuit (init, planned passes, probabilities) on the
+    whole GPU.  The output of a seeded 1 % of the variants goes to `saved`
+    for the oracle check."""
     from circuits import Gate, batch_variants
     t0 = time.perf_counter()
     vs = batch_variants(BATCH_COUNT, seed=BATCH_SEED)
@@ -347,6 +677,17 @@ def batch_leg(qsv, torch, np, steps: int, per_circuit: bool) -> dict:
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
     st = b.stats()
+    if saved is not None:
+        rng = np.random.default_rng(BATCH_CHECK_SEED)
+        idx = sorted(int(i) for i in rng.choice(
+            BATCH_COUNT, int(round(BATCH_CHECK_FRAC * BATCH_COUNT)),
+            replace=False))
+        parts = [out[int(b.offsets[i]):int(b.offsets[i + 1])].cpu().numpy()
+                 for i in idx]
+        saved["batch_idx"] = np.array(idx, np.int64)
+        saved["batch_offs"] = np.concatenate(
+            [[0], np.cumsum([len(x) for x in parts])]).astype(np.int64)
+        saved["batch_p"] = np.concatenate(parts)
     res = {"workload": (f"{BATCH_COUNT} cut variants, widths 10..20, depths "
                         f"10..60, complex64, seed {BATCH_SEED}"),
            "circuits_per_s": round(BATCH_COUNT / (ms * 1e-3), 1),
@@ -418,21 +759,27 @@ def batch_leg(qsv, torch, np, steps: int, per_circuit: bool) -> dict:
 
 # --------------------------------------------------------------- serve leg
 
-def _replay(qsv, reqs, circs, arrivals, serial: bool) -> dict:
+def _replay(qsv, reqs, circs, arrivals, serial: bool, keep=()) -> dict:
     """Submit each request at its arrival time (seconds from start) to a
-    fresh server and wait for all; latency = done - submit."""
+    fresh server and wait for all; latency = done - submit.  The results of
+    the requests whose indices are in `keep` are copied to the host and
+    returned under "_kept"."""
     import threading
     import numpy as np
     srv = qsv.Server(serial=serial)
     tickets = [None] * len(reqs)
     infos = [None] * len(reqs)
+    kept = {}
+    keep = set(keep)
     ready = threading.Semaphore(0)
 
     def waiter():
         for i in range(len(reqs)):
             ready.acquire()
             try:
-                _, info = srv.wait(tickets[i], copy=False)
+                data, info = srv.wait(tickets[i], copy=i in keep)
+                if i in keep:
+                    kept[i] = data
             except qsv.QsvError as e:   # the request completed with an error
                 info = {"failed": str(e)}
             srv.release(tickets[i])
@@ -467,14 +814,21 @@ def _replay(qsv, reqs, circs, arrivals, serial: bool) -> dict:
             "batch_launches": st["batch_launches"],
             "single_launches": st["single_launches"],
             "max_groups_in_flight": st["max_groups_in_flight"],
-            "peak_reserved_GB": round(st["peak_reserved_bytes"] / 1e9, 3)}
+            "peak_reserved_GB": round(st["peak_reserved_bytes"] / 1e9, 3),
+            "_kept": kept}
 
 
-def serve_leg(qsv, n: int) -> dict:
+SERVE_CHECK_FRAC, SERVE_CHECK_SEED, SERVE_CHECK_MAX_WIDTH = 0.05, 55, 18
+
+
+def serve_leg(qsv, n: int, saved=None) -> dict:
     """Poisson request stream (widths 8..28, depths 10..100, c64 80 %,
     probability vector or 1e4 samples): serial per-request execution
     against continuous batching, on the same seeded trace replayed at
-    0.8 and 2 times the serial service rate of those requests."""
+    0.8 and 2 times the serial service rate of those requests.  The results
+    of a seeded 5 % of the replayed requests (those up to 18 qubits, where
+    the oracle finishes in seconds) from the continuous replay at 2x go to
+    `saved` for the oracle check."""
     import numpy as np
     from circuits import layered_circuit, serve_trace
     reqs = serve_trace(n + 100, rate_per_s=1.0, seed=5)
@@ -493,16 +847,33 @@ def serve_leg(qsv, n: int) -> dict:
                         "c64 80% / c128 20%, probabilities or 1e4 samples, "
                         "Poisson arrivals (seed 5), budget 256 GB"),
            "serial_rate_per_s": mu}
+    rng = np.random.default_rng(SERVE_CHECK_SEED)
+    pick = sorted(int(i) for i in rng.choice(
+        n, max(1, int(round(SERVE_CHECK_FRAC * n))), replace=False))
+    check = [i for i in pick if reqs[100 + i].width <= SERVE_CHECK_MAX_WIDTH]
     for f in (0.8, 2.0):
         lam = f * mu
         arr = base / lam            # the unit-rate trace scaled to lam
         key = f"lambda_{f}x"
         ser = _replay(qsv, reqs[100:], circs[100:], arr, True)
+        ser.pop("_kept")
         _note(f"serve: {f}x serial done")
-        con = _replay(qsv, reqs[100:], circs[100:], arr, False)
+        con = _replay(qsv, reqs[100:], circs[100:], arr, False,
+                      keep=check if f == 2.0 else ())
+        kept = con.pop("_kept")
         _note(f"serve: {f}x continuous done")
         out[key] = {"rate_per_s": round(lam, 2), "serial": ser,
                     "continuous": con}
+    if saved is not None:
+        saved["serve"] = [
+            {"w": reqs[100 + i].width, "d": reqs[100 + i].depth,
+             "seed": reqs[100 + i].seed,
+             "shots": reqs[100 + i].shots if reqs[100 + i].want_samples else 0,
+             "prec": reqs[100 + i].precision, "data": kept[i]}
+            for i in check if i in kept and kept[i] is not None]
+        saved["serve_total"] = len(pick)
+    out["oracle_checked"] = {"sampled": len(pick), "checked": len(check),
+                             "max_width": SERVE_CHECK_MAX_WIDTH}
     return out
 
 
@@ -544,8 +915,15 @@ def main() -> int:
                     help="skip the 34-qubit / 33-qubit QFT-style leg")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the request-serving leg")
-    ap.add_argument("--serve-n", type=int, default=300,
+    ap.add_argument("--serve-n", type=int, default=2000,
                     help="requests per serving run (after 100 warm-up)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tile parameters")
+    ap.add_argument("--no-errors", action="store_true",
+                    help="skip the oracle check of the GPU results")
+    ap.add_argument("--cpu-pool-leg", type=float, default=None,
+                    help=argparse.SUPPRESS)
+    ap.add_argument("--errors-leg", default=None, help=argparse.SUPPRESS)
     a = ap.parse_args()
 
     if a.cpu_leg is not None:
@@ -556,6 +934,12 @@ def main() -> int:
         return 0
     if a.cpu_configs_leg is not None:
         print(json.dumps(cpu_configs_leg(a.cpu_configs_leg)))
+        return 0
+    if a.cpu_pool_leg is not None:
+        print(json.dumps(cpu_pool_leg(a.cpu_pool_leg)))
+        return 0
+    if a.errors_leg is not None:
+        print(json.dumps(errors_leg(a.errors_leg)))
         return 0
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); "
@@ -587,9 +971,29 @@ def main() -> int:
     state = qsv.State(n, prec, stream=stream)
     probs = torch.empty(1 << n, dtype=torch.float32, device="cuda")
     top = list(range(n - 10, n))
+    tuned = None
+    if a.strategy == "tiled" and not (a.tile_log2 or a.low_qubits or
+                                      a.reg_log2) and not a.no_autotune:
+        # choose the tile parameters for this circuit structure (outside
+        # the timed region; the state is initialised by every step)
+        _note("headline: autotuning the tile parameters")
+        best, bms, dms, _ = state.autotune(circ, opts)
+        tuned = _opts_dict(best)
+        tuned.update({"circuit_ms": round(bms, 2),
+                      "default_circuit_ms": round(dms, 2)})
+        opts = best
     state.set_profiling(True)
 
     def step():
+        # init, planned passes with the probability vector, the top-10
+        # marginal and the sampling block sums folded into the last tile
+        # pass, then the per-shot search (one call on the state's stream)
+        state.init_basis(0)
+        return state.apply_fused_outputs(
+            circ, opts, probs_ptr=probs.data_ptr(), probs_fp64=False,
+            marg_qubits=top, shots=SHOTS, seed=SAMPLE_SEED)
+
+    def step_unfolded():
         state.init_basis(0)
         state.apply_fused(circ, opts)
         state.probabilities_into(probs.data_ptr(), False)
@@ -612,21 +1016,29 @@ def main() -> int:
         pass_kind.append(kinds)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    stats = state.plan_stats()
+
+    # the same step with the outputs as separate kernels (each re-reads the
+    # state), for comparison
+    step_unfolded()
+    torch.cuda.synchronize()
+    t0u = time.perf_counter()
+    for _ in range(a.steps):
+        marg_u, smp_u = step_unfolded()
+    torch.cuda.synchronize()
+    dtu = time.perf_counter() - t0u
 
     ms_all = np.concatenate(pass_ms)
     kinds_all = np.concatenate(pass_kind)
     state_bytes = b << n
-    # algorithmic bytes of one step
-    step_bytes = (state_bytes                      # init (write)
-                  + stats["alg_bytes"]             # gate passes
-                  + state_bytes + (4 << n)         # probabilities
-                  + state_bytes                    # marginal (read)
-                  + state_bytes                    # sampling block sums
-                  + SHOTS * (b << 10))             # per-shot block reread
+    # algorithmic bytes of one step: what the method must move (the state
+    # written by init, every pass's read + write, the probability vector
+    # written); the marginal and the block sums come out of the last pass
+    step_bytes = state_bytes + stats["alg_bytes"] + (4 << n)
     ms_per_step = dt / a.steps * 1e3
     value = step_bytes * a.steps / dt / 1e9
 
-    # dominant kernel: the tile pass (or the kind with most time)
+    # dominant kernel: the kind of pass with most time
     kind_names = {1: "dense/diag (plain)", 2: "tile_kernel", 3: "fused"}
     tot = {k: float(ms_all[kinds_all == k].sum()) for k in (1, 2, 3)}
     dom = max(tot, key=tot.get)
@@ -639,13 +1051,20 @@ def main() -> int:
         [m.sum() for m in pass_ms])) * 1e-3) / 1e9
     circuit_ms = float(np.mean([m.sum() for m in pass_ms]))
 
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE) and dom == 2 and prec == qsv.QSV_C64:
-        with open(TRAFFIC_FILE) as f:
-            tr = json.load(f)
-        if tr.get("kernel_source_sha256_16") == _src_hash(TILE_SRC) and \
-                tr.get("strategy") == a.strategy:
-            traffic = tr.get("bytes_per_launch")
+    traffic = counters = None
+    if dom == 2 and prec == qsv.QSV_C64:
+        h = _src_hash(TILE_SRC)
+        for fn, key in ((TRAFFIC_FILE, "traffic"), (COUNTER_FILE, "counters")):
+            if not os.path.exists(fn):
+                continue
+            with open(fn) as f:
+                tr = json.load(f)
+            if tr.get("kernel_source_sha256_16") == h and \
+                    tr.get("strategy") == a.strategy:
+                if key == "traffic":
+                    traffic = tr.get("bytes_per_launch")
+                else:
+                    counters = tr.get("per_dispatch")
 
     if a.copy_probe:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
@@ -655,6 +1074,44 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if dom == 2:
+        # the tile pass is bound by vector-ALU issue: its arithmetic against
+        # the chip's FP32/FP64 FMA rate (packed FP32 is not used), with the
+        # HBM figures of the same launches beside it
+        # the planner's count of the arithmetic its tile ops define, per
+        # launch (one step's tile passes)
+        tflop = stats["tile_flops"] / max(1, stats["tile_passes"])
+        roof = {"bound": "alu",
+                "achieved": round(tflop / (avg_ms * 1e-3) / 1e12, 2),
+                "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tflop / (avg_ms * 1e-3) / 1e12 /
+                              PEAK_VALU_TFLOPS, 4),
+                "traffic": traffic,
+                "kernel": kind_names[dom],
+                "flops_per_launch": tflop,
+                "avg_launch_ms": round(avg_ms, 4),
+                "launches": int(sel.size),
+                "hbm": {"achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
+                        "unit": "GB/s",
+                        "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                        "bytes_per_launch": per_launch,
+                        "traffic": traffic}}
+        if counters and "SQ_INSTS_VALU" in counters:
+            # wave64 VALU instructions take 4 cycles of one SIMD; 1024 SIMDs
+            roof["valu_issue_frac"] = round(
+                counters["SQ_INSTS_VALU"] * 4 /
+                (1024 * CLOCK_HZ * avg_ms * 1e-3), 4)
+            roof["valu_insts_per_wave"] = round(
+                counters["SQ_INSTS_VALU"] / counters.get("SQ_WAVES", 1), 1)
+    else:
+        roof = {"bound": "hbm", "achieved": round(achieved, 1),
+                "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                "traffic": traffic, "kernel": kind_names[dom],
+                "bytes_per_launch": per_launch,
+                "avg_launch_ms": round(avg_ms, 4),
+                "launches": int(sel.size)}
 
     out = {
         "metric": METRIC,
@@ -675,24 +1132,26 @@ def main() -> int:
                          f"{'complex64' if b == 8 else 'complex128'}, "
                          f"{a.strategy} plan; step = init + gate passes + "
                          f"probabilities + top-10 marginal + "
-                         f"{SHOTS} samples"),
+                         f"{SHOTS} samples, outputs folded into the last "
+                         f"tile pass"),
             "n_qubits": n, "depth": DEPTH, "gates": len(gates),
             "strategy": a.strategy, "parallelism": "single GPU",
         },
+        "step_bytes": step_bytes,
+        "ms_per_step_outputs_unfolded": round(dtu / a.steps * 1e3, 3),
+        "folded_outputs": stats["folded_outputs"],
+        "folded_vs_unfolded_marginal_max_abs": float(
+            np.max(np.abs(marg - marg_u))),
+        "folded_vs_unfolded_shots_differ": int(np.count_nonzero(smp != smp_u)),
         "depth40_circuit_ms": round(circuit_ms, 3),
         "gate_pass_GBps": round(gate_pass_gbps, 1),
         "gate_pass_pct_of_peak": round(100 * gate_pass_gbps / PEAK_HBM_GBPS, 1),
         "passes": stats["passes"], "tile_segments": stats["segments"],
+        "tile_ops": stats["tile_ops"],
         "plan_ms": round(stats["plan_ns"] / 1e6, 3),
+        "autotuned": tuned,
         "top10_marginal_sum": float(np.sum(marg)),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
-                     "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBPS, 4),
-                     "traffic": traffic,
-                     "kernel": kind_names[dom],
-                     "bytes_per_launch": per_launch,
-                     "avg_launch_ms": round(avg_ms, 4),
-                     "launches": int(sel.size)},
+        "roofline": roof,
     }
     # further outputs of the final state (outside the timed step)
     t0 = time.perf_counter()
@@ -761,6 +1220,10 @@ def main() -> int:
     state.free()
     del probs
     torch.cuda.empty_cache()
+    saved = {}
+    if not a.no_cpu_baseline and not a.no_errors:
+        _note("errors: GPU results for the oracle check")
+        errors_inputs(qsv, torch, np, saved)
     if not a.no_plans:
         _note("plans leg")
         out["plans"] = plans_leg(qsv, torch, np, circ, n)
@@ -776,14 +1239,20 @@ def main() -> int:
     if not a.no_batch:
         _note("batch leg")
         out["batch"] = batch_leg(qsv, torch, np, max(1, a.steps),
-                                 not a.no_per_circuit)
+                                 not a.no_per_circuit, saved)
     if not a.no_serve:
         _note("serve leg")
-        out["serve"] = serve_leg(qsv, a.serve_n)
+        out["serve"] = serve_leg(qsv, a.serve_n, saved)
     if not a.no_cpu_baseline:
         _note("cpu baseline (oracle)")
+        edir = write_errors_inputs(np, saved) if saved else None
         out["cpu_baseline"] = run_cpu_baseline(
-            a.cpu_budget, 0.0 if a.no_batch else a.cpu_batch_budget)
+            a.cpu_budget, 0.0 if a.no_batch else a.cpu_batch_budget, edir)
+        if edir:
+            import shutil
+            shutil.rmtree(edir, ignore_errors=True)
+        if "errors" in out["cpu_baseline"]:
+            out["errors"] = out["cpu_baseline"].pop("errors")
         cb = out["cpu_baseline"].get("batch") or {}
         if "batch" in out and cb.get("circuits_per_s"):
             out["batch"]["speedup_vs_oracle_cpu"] = round(

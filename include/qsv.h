@@ -216,8 +216,10 @@ qsv_status qsv_apply_fused_outputs(qsv_state s, const qsv_circuit* circ,
  *   out[9] phase blocks (runs of diagonal gates applied as one phase
  *   polynomial), out[10] diagonal gates inside phase blocks, out[11] the
  *   outputs the last pass folded (qsv_apply_fused_outputs: bit 0
- *   probabilities, bit 1 marginal, bit 2 shots).
- *   n_out <= 12 entries. */
+ *   probabilities, bit 1 marginal, bit 2 shots), out[12] real flops the
+ *   tile ops define (14 per amplitude a dense 2x2 op changes, 6 per
+ *   amplitude a diagonal op, phase op or phase block multiplies).
+ *   n_out <= 13 entries. */
 qsv_status qsv_last_plan_stats(qsv_state s, uint64_t* out, int32_t n_out);
 
 /* Per-pass timing of the passes of Section III.B's cache-blocked plan.
@@ -230,6 +232,31 @@ qsv_status qsv_last_plan_stats(qsv_state s, uint64_t* out, int32_t n_out);
 qsv_status qsv_set_profiling(qsv_state s, int32_t enable);
 qsv_status qsv_pass_times(qsv_state s, float* ms_out, int32_t* kinds_out,
                           int32_t cap, int32_t* count);
+
+/* Autotuning of the chunk parameters of Section III.B's cache blocking
+ * (the evaluator of Section IV.A fixes its blocking qubits per machine;
+ * here the tile size, the low qubits of every tile and the amplitudes per
+ * thread are chosen per state width, precision and circuit structure).
+ * Plans the circuit under the defaults and under every valid (tile_log2,
+ * low_qubits, reg_log2), ranks the latter by a cost model, and times the
+ * defaults and the best-ranked candidates, max_timed in all (0: 6; at most
+ * 64), one run each after one untimed run: the kernel time of the passes,
+ * by HIP events.  The fastest wins if it beats the defaults by 2 % or more,
+ * else the defaults stay.  Runs the circuit on the state, so the state's
+ * contents are overwritten (initialise it again afterwards); blocks until
+ * the runs finish.  base: strategy and k_max (NULL: defaults; other fields
+ * ignored).  The result is cached per (device, n, precision, strategy,
+ * k_max, circuit structure: gate shapes, qubits and diagonal form, not the
+ * matrix values); a cached call runs nothing and sets *from_cache = 1.
+ * Outputs: *best (filled options for qsv_apply_fused), *best_ms and
+ * *default_ms (may be NULL), *from_cache (may be NULL).  Errors:
+ * QSV_ERR_INVALID_ARG for a NULL best, max_timed outside 0..64 or a bad
+ * circuit, QSV_ERR_UNSUPPORTED for an unknown strategy, QSV_ERR_DEVICE if a
+ * run fails. */
+qsv_status qsv_autotune_fused(qsv_state s, const qsv_circuit* circ,
+                              const qsv_fuse_opts* base, int32_t max_timed,
+                              qsv_fuse_opts* best, float* best_ms,
+                              float* default_ms, int32_t* from_cache);
 
 /* Host-only planner dry run of the cache blocking of Section III.B (no
  * device work; usable without a GPU).
@@ -250,8 +277,9 @@ qsv_status qsv_plan_describe(const qsv_circuit* circ, int32_t n_qubits,
  * circuit as qsv_apply_fused would (the cache-blocking transpilation of
  * Section III.B) and builds its tile programs, then writes out[0] passes,
  * out[1] tile passes, out[2] tile segments, out[3] tile ops, out[4] phase
- * blocks, out[5] diagonal gates inside phase blocks (host array; n_out <= 6
- * entries).  QSV_ERR_UNSUPPORTED for an unknown precision,
+ * blocks, out[5] diagonal gates inside phase blocks, out[6] real flops the
+ * tile ops define (as out[12] of qsv_last_plan_stats) (host array;
+ * n_out <= 7 entries).  QSV_ERR_UNSUPPORTED for an unknown precision,
  * QSV_ERR_INVALID_ARG for a bad circuit, option, n_qubits or buffer. */
 qsv_status qsv_plan_program_stats(const qsv_circuit* circ, int32_t n_qubits,
                                   int32_t prec, const qsv_fuse_opts* opts,

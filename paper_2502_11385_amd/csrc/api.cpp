@@ -8,7 +8,9 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "device_common.h"
@@ -39,7 +41,7 @@ struct qsv_state_s {
   // reduction scratch
   char* scratch = nullptr;
   size_t scratch_cap = 0;
-  uint64_t stats[12] = {0};
+  uint64_t stats[13] = {0};
   // per-pass timing
   bool profiling = false;
   std::vector<hipEvent_t> evs;
@@ -739,6 +741,7 @@ static qsv_status apply_fused_impl(qsv_state s, const qsv_circuit* circ,
   s->stats[9] = est.blocks;
   s->stats[10] = est.block_gates;
   s->stats[11] = 0;
+  s->stats[12] = uint64_t(std::ldexp(est.flops_per_amp, n) + 0.5);
   if (!outs) return QSV_OK;
 
   // ---- outputs: finish the folded reductions, run the others
@@ -851,9 +854,192 @@ qsv_status qsv_pass_times(qsv_state s, float* ms_out, int32_t* kinds_out,
   return QSV_OK;
 }
 
+// ---- autotuning of the blocking parameters
+
+namespace {
+
+// Structure of a circuit: what the plan depends on (gate shapes, qubits,
+// diagonal form), not the matrix values.  FNV-1a over those fields.
+uint64_t circuit_signature(const std::vector<HostGate>& G) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (v >> (8 * i)) & 0xFF;
+      h *= 1099511628211ull;
+    }
+  };
+  mix(G.size());
+  for (const HostGate& g : G) {
+    mix(uint64_t(g.k) | uint64_t(g.c) << 8 | uint64_t(g.diagonal) << 16 |
+        uint64_t(g.masked_phase) << 17);
+    for (int i = 0; i < g.k; ++i) mix(uint64_t(g.t[i]));
+    for (int i = 0; i < g.c; ++i) mix(uint64_t(g.ctl[i]));
+  }
+  return h;
+}
+
+struct TuneKey {
+  int device, n, prec, strategy, k_max;
+  uint64_t sig;
+  bool operator==(const TuneKey& o) const {
+    return device == o.device && n == o.n && prec == o.prec &&
+           strategy == o.strategy && k_max == o.k_max && sig == o.sig;
+  }
+};
+struct TuneKeyHash {
+  size_t operator()(const TuneKey& k) const {
+    return size_t(k.sig ^ (uint64_t(k.n) << 40) ^ (uint64_t(k.prec) << 48) ^
+                  (uint64_t(k.device) << 52) ^ (uint64_t(k.strategy) << 56) ^
+                  (uint64_t(k.k_max) << 60));
+  }
+};
+struct TuneEntry {
+  qsv_fuse_opts best;
+  float best_ms, default_ms;
+};
+std::mutex g_tune_mu;
+std::unordered_map<TuneKey, TuneEntry, TuneKeyHash> g_tune;
+
+// Modelled time of a plan (seconds), for ranking candidates before any is
+// timed: a tile pass costs the larger of its HBM time and its vector-ALU
+// issue time (eight FMA instructions per amplitude and dense op, a
+// re-layout per segment, a fixed part), a fused or plain pass its HBM time.
+double plan_model_s(const std::vector<HostGate>& G, const Plan& plan, int n,
+                    int bytes, const PlanOptions& po) {
+  const double state = std::ldexp(double(bytes), n);
+  const double hbm = 6.0e12, issue = 1024 * 2.4e9 * 0.85;
+  const double amps_per_thread = double(1 << po.reg_log2);
+  const double waves = std::ldexp(1.0, n) / amps_per_thread / 64;
+  double t = 0;
+  for (const Pass& p : plan.passes) {
+    double tp = double(p.alg_bytes) / hbm;
+    if (p.kind == kPassTile) {
+      std::vector<TilePass> tps;
+      std::vector<TileSeg> tss;
+      std::vector<TileOp> tos;
+      TileEmitStats e;
+      if (!emit_tile_pass(p, G, po.reg_log2, &tps, &tss, &tos, &e).empty())
+        return 1e30;
+      const double insts = double(e.ops) * amps_per_thread * 8 * (bytes / 8) +
+                           double(p.segs.size() + 1) * amps_per_thread * 6 +
+                           250;
+      tp = std::max(2 * state / hbm, waves * insts * 4 / issue);
+    }
+    t += tp + 4e-6;
+  }
+  return t;
+}
+
+}  // namespace
+
+qsv_status qsv_autotune_fused(qsv_state s, const qsv_circuit* circ,
+                              const qsv_fuse_opts* base, int32_t max_timed,
+                              qsv_fuse_opts* best, float* best_ms,
+                              float* default_ms, int32_t* from_cache) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  if (!best) return fail(QSV_ERR_INVALID_ARG, "null best");
+  if (max_timed < 0 || max_timed > 64)
+    return fail(QSV_ERR_INVALID_ARG, "max_timed must be 0..64");
+  if (max_timed == 0) max_timed = 6;
+  std::vector<HostGate> G;
+  if ((st = parse_circuit(circ, s->n, &G)) != QSV_OK) return st;
+  qsv_fuse_opts b0 = {};
+  if (base) {
+    b0.strategy = base->strategy;
+    b0.k_max = base->k_max;
+  }
+  PlanOptions pdef;
+  {
+    int v[5] = {b0.strategy, 0, b0.k_max, 0, 0};
+    std::string err = resolve_options(s->n, s->b, v, &pdef);
+    if (!err.empty())
+      return fail(b0.strategy < 0 || b0.strategy > 3 ? QSV_ERR_UNSUPPORTED
+                                                     : QSV_ERR_INVALID_ARG,
+                  err);
+  }
+  const TuneKey key{s->device, s->n, s->prec, pdef.strategy, pdef.k_max,
+                    circuit_signature(G)};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      *best = it->second.best;
+      if (best_ms) *best_ms = it->second.best_ms;
+      if (default_ms) *default_ms = it->second.default_ms;
+      if (from_cache) *from_cache = 1;
+      return QSV_OK;
+    }
+  }
+  // candidates: the defaults first, then every valid (tile_log2,
+  // low_qubits, reg_log2) ranked by the model; the plain and fused
+  // strategies have no tile parameters to choose
+  struct Cand {
+    qsv_fuse_opts o;
+    double model;
+  };
+  std::vector<Cand> cands;
+  const qsv_fuse_opts def = {pdef.strategy, pdef.tile_log2, pdef.k_max,
+                             pdef.low_qubits, pdef.reg_log2};
+  cands.push_back({def, 0});
+  if (pdef.strategy == QSV_PLAN_AUTO || pdef.strategy == QSV_PLAN_TILED) {
+    std::vector<Cand> more;
+    for (int L = 10; L <= 13; ++L)
+      for (int rb = 3; rb <= 5; ++rb)
+        for (int low = 2; low <= 6; ++low) {
+          const int v[5] = {pdef.strategy, L, pdef.k_max, low, rb};
+          PlanOptions po;
+          if (!resolve_options(s->n, s->b, v, &po).empty()) continue;
+          if (L == pdef.tile_log2 && rb == pdef.reg_log2 &&
+              low == pdef.low_qubits)
+            continue;
+          Plan plan;
+          make_plan(G, s->n, s->b, po, &plan);
+          more.push_back({{pdef.strategy, L, pdef.k_max, low, rb},
+                          plan_model_s(G, plan, s->n, s->b, po)});
+        }
+    std::sort(more.begin(), more.end(),
+              [](const Cand& a, const Cand& c) { return a.model < c.model; });
+    for (size_t i = 0; i < more.size() && int(cands.size()) < max_timed; ++i)
+      cands.push_back(more[i]);
+  }
+  // time each candidate once (kernel time of its passes, HIP events), after
+  // one untimed run of the defaults; the state's contents are overwritten
+  const bool prof = s->profiling;
+  s->profiling = true;
+  std::vector<float> ms(cands.size(), 0.0f);
+  for (size_t i = 0; i <= cands.size() && st == QSV_OK; ++i) {
+    const qsv_fuse_opts& o = cands[i == 0 ? 0 : i - 1].o;
+    st = apply_fused_impl(s, circ, &o, nullptr);
+    if (st != QSV_OK || i == 0) continue;
+    std::vector<float> pm(size_t(std::max(s->ev_used, 1)));
+    int32_t cnt = 0;
+    st = qsv_pass_times(s, pm.data(), nullptr, int32_t(pm.size()), &cnt);
+    float tot = 0;
+    for (int32_t j = 0; j < cnt; ++j) tot += pm[size_t(j)];
+    ms[i - 1] = tot;
+  }
+  s->profiling = prof;
+  if (st != QSV_OK) return st;
+  // the defaults stay unless a candidate is at least 2 % faster
+  size_t bi = 0;
+  for (size_t i = 1; i < cands.size(); ++i)
+    if (ms[i] < ms[bi] && ms[i] < 0.98f * ms[0]) bi = i;
+  const TuneEntry e{cands[bi].o, ms[bi], ms[0]};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = e;
+  }
+  *best = e.best;
+  if (best_ms) *best_ms = e.best_ms;
+  if (default_ms) *default_ms = e.default_ms;
+  if (from_cache) *from_cache = 0;
+  return QSV_OK;
+}
+
 qsv_status qsv_last_plan_stats(qsv_state s, uint64_t* out, int32_t n_out) {
   if (!s) return fail(QSV_ERR_INVALID_ARG, "null state");
-  if (!out || n_out < 0 || n_out > 12)
+  if (!out || n_out < 0 || n_out > 13)
     return fail(QSV_ERR_INVALID_ARG, "bad stats buffer");
   for (int i = 0; i < n_out; ++i) out[i] = s->stats[i];
   return QSV_OK;
@@ -896,7 +1082,7 @@ qsv_status qsv_plan_program_stats(const qsv_circuit* circ, int32_t n,
     return fail(QSV_ERR_UNSUPPORTED, "unknown precision");
   if (n < 1 || n > QSV_MAX_QUBITS)
     return fail(QSV_ERR_INVALID_ARG, "n_qubits must be 1..34");
-  if (!out || n_out < 0 || n_out > 6)
+  if (!out || n_out < 0 || n_out > 7)
     return fail(QSV_ERR_INVALID_ARG, "bad stats buffer");
   std::vector<HostGate> G;
   PlanOptions po;
@@ -912,8 +1098,9 @@ qsv_status qsv_plan_program_stats(const qsv_circuit* circ, int32_t n,
     std::string err = emit_tile_pass(p, G, po.reg_log2, &tp, &ts, &to, &est);
     if (!err.empty()) return fail(QSV_ERR_DEVICE, err);
   }
-  const uint64_t v[6] = {plan.passes.size(), tp.size(), ts.size(), est.ops,
-                         est.blocks, est.block_gates};
+  const uint64_t v[7] = {plan.passes.size(), tp.size(), ts.size(), est.ops,
+                         est.blocks, est.block_gates,
+                         uint64_t(std::ldexp(est.flops_per_amp, n) + 0.5)};
   for (int i = 0; i < n_out; ++i) out[i] = v[i];
   return QSV_OK;
 }

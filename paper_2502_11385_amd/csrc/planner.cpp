@@ -365,6 +365,14 @@ std::string set_op_code(TileOp* op) {
   }
 }
 
+// Exactly the 2x2 identity (interleaved complex, row-major).
+static bool is_identity2(const double* m) {
+  static const double id[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+  for (int i = 0; i < 8; ++i)
+    if (m[i] != id[i]) return false;
+  return true;
+}
+
 std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
                            int RB, std::vector<TilePass>* tpasses,
                            std::vector<TileSeg>* tsegs,
@@ -868,7 +876,26 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
       if (!err.empty()) return err;
     }
   }
-  if (stats) stats->ops += tops->size() - size_t(op_base);
+  if (stats) {
+    stats->ops += tops->size() - size_t(op_base);
+    for (size_t i = size_t(op_base); i < tops->size(); ++i) {
+      const TileOp& o = (*tops)[i];
+      // fraction of the amplitudes the op touches: its controls must be 1
+      // (a phase op's masks hold its targets too)
+      double frac = std::ldexp(
+          1.0, -(__builtin_popcount(o.lctrl) + __builtin_popcountll(o.gctrl)));
+      if (o.kind == kOpDense1 && o.mux != kMuxNone) {
+        // a mux op applies m on half of those amplitudes and m2 on the
+        // other half; an identity half changes nothing
+        frac *= 0.5 * ((is_identity2(o.m) ? 0 : 1) +
+                       (is_identity2(o.m2) ? 0 : 1));
+      } else if (o.kind == kOpDense1 && is_identity2(o.m)) {
+        frac = 0;
+      }
+      stats->flops_per_amp += (o.kind == kOpDense1 ? 14.0 : 6.0) *
+                              (o.kind == kOpPhaseBlock ? 1.0 : frac);
+    }
+  }
   // Phase-block records follow the pass's ops, in whole TileOp slots.
   for (const Blob& bl : blobs) {
     const size_t at = tops->size();

@@ -76,6 +76,12 @@ struct TileEmitStats {
   uint64_t ops = 0;          // tile ops (phase-block data records excluded)
   uint64_t blocks = 0;       // kOpPhaseBlock ops
   uint64_t block_gates = 0;  // diagonal gates applied inside phase blocks
+  // Real flops per state amplitude that the ops define: a 2x2 complex
+  // matrix row (14: two complex products and a sum) per amplitude a dense
+  // op changes, a complex product (6) per amplitude a diagonal op, a phase
+  // op or a phase block multiplies.  Times 2^n it is the arithmetic of the
+  // tile passes.
+  double flops_per_amp = 0;
 };
 
 // Append the device records of one tile pass (its TilePass, segments and

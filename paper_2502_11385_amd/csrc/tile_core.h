@@ -287,6 +287,32 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Byte address of a shared-memory pointer in the LDS address space.
+template <typename C>
+__device__ __forceinline__ uint32_t lds_address(const C* p) {
+  return uint32_t(size_t((const __attribute__((address_space(3))) C*)p));
+}
+
+// Store and load one complex amplitude at LDS byte address `at` (as a
+// two-element vector of its component type).
+template <typename C>
+__device__ __forceinline__ void lds_store(uint32_t at, const C& v) {
+  using E = decltype(v.x);
+  typedef E V __attribute__((ext_vector_type(2)));
+  V w;
+  w.x = v.x;
+  w.y = v.y;
+  *(__attribute__((address_space(3))) V*)(size_t(at)) = w;
+}
+template <typename C>
+__device__ __forceinline__ void lds_load(uint32_t at, C& v) {
+  using E = decltype(v.x);
+  typedef E V __attribute__((ext_vector_type(2)));
+  const V w = *(const __attribute__((address_space(3))) V*)(size_t(at));
+  v.x = w.x;
+  v.y = w.y;
+}
+
 // Move the tile from layout `from` to layout `to` through LDS.
 // Threads with active == false (beyond the tile) only join the barriers.
 template <typename T, int RB, typename C>
@@ -296,23 +322,36 @@ __device__ __forceinline__ void relayout(C* a, C* lds, const Layout<RB>& from,
   constexpr int R = 1 << RB;
   // The thread and register parts of a tile index have disjoint bits and
   // the swizzle is linear over XOR: swz(rt | o_j) = swz(rt) ^ swz(o_j), one
-  // per-thread term and one uniform term per register.
-  char* lb = reinterpret_cast<char*>(lds);
+  // per-thread term and one uniform term per register.  The kernels place
+  // no other shared variable before the tile, so it starts at LDS address
+  // 0 and each access is one XOR of the two terms; otherwise the base is
+  // added (a uniform branch).
+  const uint32_t lb = lds_address(lds);
   uint32_t so[R];
   if (active) {
     lds_reg_offsets<T, RB>(from, so);
     const uint32_t rf =
         lds_swz<T>(thread_local_base(from, tid)) * uint32_t(sizeof(C));
+    if (lb == 0) {
 #pragma unroll
-    for (int j = 0; j < R; ++j) *reinterpret_cast<C*>(lb + (rf ^ so[j])) = a[j];
+      for (int j = 0; j < R; ++j) lds_store(rf ^ so[j], a[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < R; ++j) lds_store(lb + (rf ^ so[j]), a[j]);
+    }
   }
   lds_barrier();
   if (active) {
     lds_reg_offsets<T, RB>(to, so);
     const uint32_t rt =
         lds_swz<T>(thread_local_base(to, tid)) * uint32_t(sizeof(C));
+    if (lb == 0) {
 #pragma unroll
-    for (int j = 0; j < R; ++j) a[j] = *reinterpret_cast<const C*>(lb + (rt ^ so[j]));
+      for (int j = 0; j < R; ++j) lds_load(rt ^ so[j], a[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < R; ++j) lds_load(lb + (rt ^ so[j]), a[j]);
+    }
   }
   lds_barrier();
 }

@@ -46,7 +46,7 @@ EXPORTED = [
     "qsv_gate_matrix", "qsv_probabilities", "qsv_norm", "qsv_renormalize",
     "qsv_marginal", "qsv_sample", "qsv_get_amplitudes", "qsv_set_amplitudes",
     "qsv_info", "qsv_sync", "qsv_last_error", "qsv_version",
-    "qsv_set_profiling", "qsv_pass_times",
+    "qsv_set_profiling", "qsv_pass_times", "qsv_autotune_fused",
     "qsv_batch_create", "qsv_batch_out_offsets", "qsv_batch_launch",
     "qsv_batch_stats", "qsv_batch_free", "qsv_gate_matrices",
     "qsv_server_create", "qsv_server_submit", "qsv_server_wait",
@@ -182,6 +182,9 @@ _SIGS = {
     "qsv_server_stats": [_p, _pu64, _i32],
     "qsv_server_destroy": [_p],
     "qsv_pass_times": [_p, C.POINTER(C.c_float), _pi32, _i32, _pi32],
+    "qsv_autotune_fused": [_p, C.POINTER(qsv_circuit), C.POINTER(qsv_fuse_opts),
+                           _i32, C.POINTER(qsv_fuse_opts),
+                           C.POINTER(C.c_float), C.POINTER(C.c_float), _pi32],
     "qsv_top_k": [_p, C.c_uint32, _pu64, _pd],
     "qsv_permute_qubits": [_p, _pi32],
     "qsv_expectation_pauli": [_p, _i32, _pu64, _pu64, _pd],
@@ -354,13 +357,13 @@ def plan_program_stats(circ: Circuit, n: int, prec: int = QSV_C64,
                        opts: Optional[qsv_fuse_opts] = None) -> dict:
     """Host-only dry run of the device program: pass, tile-pass, segment,
     op and phase-block counts."""
-    out = np.zeros(6, np.uint64)
+    out = np.zeros(7, np.uint64)
     st = circ.struct()
     _check(_lib.qsv_plan_program_stats(
         C.byref(st), n, prec, C.byref(opts) if opts is not None else None,
-        _ptr(out, C.c_uint64), 6))
+        _ptr(out, C.c_uint64), 7))
     keys = ("passes", "tile_passes", "segments", "tile_ops", "phase_blocks",
-            "block_gates")
+            "block_gates", "tile_flops")
     return {k: int(v) for k, v in zip(keys, out)}
 
 
@@ -465,12 +468,27 @@ class State:
             C.byref(o)))
         return marg, smp
 
+    def autotune(self, circ: Circuit, opts: Optional[qsv_fuse_opts] = None,
+                 max_timed: int = 0):
+        """Choose the tile parameters for this circuit's structure by timing
+        candidates on this state (its contents are overwritten).  Returns
+        (options, best_ms, default_ms, from_cache)."""
+        st = circ.struct()
+        best = qsv_fuse_opts()
+        bms, dms = C.c_float(0), C.c_float(0)
+        cached = C.c_int32(0)
+        _check(_lib.qsv_autotune_fused(
+            self._h, C.byref(st), C.byref(opts) if opts is not None else None,
+            int(max_timed), C.byref(best), C.byref(bms), C.byref(dms),
+            C.byref(cached)))
+        return best, float(bms.value), float(dms.value), bool(cached.value)
+
     def plan_stats(self) -> dict:
-        out = np.zeros(12, np.uint64)
-        _check(_lib.qsv_last_plan_stats(self._h, _ptr(out, C.c_uint64), 12))
+        out = np.zeros(13, np.uint64)
+        _check(_lib.qsv_last_plan_stats(self._h, _ptr(out, C.c_uint64), 13))
         keys = ("passes", "gates", "alg_bytes", "tile_passes", "plain_passes",
                 "fused_passes", "segments", "plan_ns", "tile_ops",
-                "phase_blocks", "block_gates", "folded_outputs")
+                "phase_blocks", "block_gates", "folded_outputs", "tile_flops")
         return {k: int(v) for k, v in zip(keys, out)}
 
     def set_profiling(self, enable: bool):

@@ -2,7 +2,8 @@
 
   python -m paper_2502_11385_amd.rocprof_summary stats DB
       per-kernel calls / total / average duration (kernel-trace run)
-  python -m paper_2502_11385_amd.rocprof_summary counters DB --kernel NAME
+  python -m paper_2502_11385_amd.rocprof_summary counters DB --kernel NAME \
+        [--json OUT --source FILES...]
       per-counter averages per dispatch (and per wave with SQ_WAVES) of one
       kernel in a --pmc run
   python -m paper_2502_11385_amd.rocprof_summary traffic FETCH_DB WRITE_DB \
@@ -125,13 +126,27 @@ def main() -> int:
     k = sub.add_parser("counters")
     k.add_argument("db")
     k.add_argument("--kernel", default="tile_kernel")
+    k.add_argument("--json", default=None)
+    k.add_argument("--source", default=None, nargs="+",
+                   help="kernel source files whose combined hash is recorded")
+    k.add_argument("--strategy", default="tiled")
     a = ap.parse_args()
     if a.cmd == "counters":
+        rows = counters(a.db, a.kernel)
         print(f"{'counter':24s} {'dispatches':>10} {'avg/dispatch':>16} "
               f"{'avg/wave':>12}")
-        for c, nd, avg, pw in counters(a.db, a.kernel):
+        for c, nd, avg, pw in rows:
             pws = f"{pw:12.2f}" if pw is not None else f"{'':>12}"
             print(f"{c:24s} {nd:10d} {avg:16.1f} {pws}")
+        if a.json:
+            r = {"kernel": a.kernel,
+                 "per_dispatch": {c: avg for c, _, avg, _ in rows},
+                 "dispatches": max((nd for _, nd, _, _ in rows), default=0)}
+            if a.source:
+                r["kernel_source_sha256_16"] = sources_hash(a.source)
+                r["strategy"] = a.strategy
+            with open(a.json, "w") as f:
+                json.dump(r, f, indent=1)
         return 0
     if a.cmd == "stats":
         print(f"{'calls':>6} {'total_ms':>10} {'avg_us':>10}  kernel")

@@ -119,12 +119,27 @@ def test_plan_option_validation():
     assert e.value.status == qsv.QSV_ERR_UNSUPPORTED
 
 
+def test_plan_program_stats_diagonal_flops():
+    # CZ multiplies the quarter of the amplitudes with both bits 1; a
+    # general one-qubit diagonal multiplies every amplitude (6 flops each)
+    Z = np.diag([1, -1]).astype(complex)
+    rz = np.diag([np.exp(-0.3j), np.exp(0.3j)])
+    opts = qsv.fuse_opts(strategy=qsv.PLAN_TILED)
+    st = qsv.plan_program_stats(_circ([([1], [0], Z)]), 8, qsv.QSV_C64, opts)
+    assert st["tile_flops"] == 6 * 64
+    st = qsv.plan_program_stats(_circ([([2], [], rz)]), 8, qsv.QSV_C64, opts)
+    assert st["tile_flops"] == 6 * 256
+
+
 def test_plan_program_stats_validation():
     c = _circ([([0], [], X), ([1], [0], X)])
     st = qsv.plan_program_stats(c, 8, qsv.QSV_C64,
                                 qsv.fuse_opts(strategy=qsv.PLAN_TILED))
     assert st["passes"] == 1 and st["tile_passes"] == 1
     assert st["tile_ops"] >= 1 and st["phase_blocks"] == 0
+    # X changes every amplitude, CX the half whose control is 1: one 2x2
+    # complex row each (14 flops)
+    assert st["tile_flops"] == 14 * 256 + 14 * 128
     with pytest.raises(qsv.QsvError) as e:
         qsv.plan_program_stats(c, 8, prec=7)
     assert e.value.status == qsv.QSV_ERR_UNSUPPORTED
@@ -137,6 +152,6 @@ def test_plan_program_stats_validation():
     st = c.struct()
     assert qsv._lib.qsv_plan_program_stats(
         C.byref(st), 8, qsv.QSV_C64, None,
-        out.ctypes.data_as(C.POINTER(C.c_uint64)), 7) == qsv.QSV_ERR_INVALID_ARG
+        out.ctypes.data_as(C.POINTER(C.c_uint64)), 8) == qsv.QSV_ERR_INVALID_ARG
     assert qsv._lib.qsv_plan_program_stats(
         C.byref(st), 8, qsv.QSV_C64, None, None, 1) == qsv.QSV_ERR_INVALID_ARG
