@@ -332,6 +332,19 @@ qsv_status qsv_norm(qsv_state s, double* out);
  * norm, QSV_ERR_DEVICE for a failed state. */
 qsv_status qsv_renormalize(qsv_state s, double* norm_out);
 
+/* (For callers that cannot allocate.)  qsv_renormalize for callers that
+ * may not allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid allocation): the same kernels and
+ * the same result bit for bit, with the norm's partial sums in a fixed
+ * scratch array of 4 MiB + 256 B that the library holds on each device
+ * until the process ends, so no call allocates or frees memory.  That bounds the
+ * state to 30 qubits (2^18 partial pairs); wider states return
+ * QSV_ERR_INVALID_ARG and nothing runs.  All calls on one device share the
+ * array: calls that overlap on one device (states on different streams or
+ * host threads) race and must be serialised by the caller.  Other errors
+ * as qsv_renormalize. */
+qsv_status qsv_renormalize_noalloc(qsv_state s, double* norm_out);
+
 /* Marginal distribution of the specified qubits (the Builder's
  * distribution of specified qubits, Section IV.A):
  *   out[j] = sum of p_i over i with bit qubits[l] of i == bit l of j,

@@ -1390,6 +1390,32 @@ qsv_status qsv_renormalize(qsv_state s, double* norm_out) {
   return QSV_OK;
 }
 
+qsv_status qsv_renormalize_noalloc(qsv_state s, double* norm_out) {
+  qsv_status st = check_state(s);
+  if (st != QSV_OK) return st;
+  const size_t part = (norm_scratch_bytes(s->n) + 255) & ~size_t(255);
+  if (part + sizeof(double) > fixed_scratch_bytes())
+    return fail(QSV_ERR_INVALID_ARG,
+                "state too large for the fixed scratch (at most 30 qubits)");
+  if ((st = select_device(s)) != QSV_OK) return st;
+  void* base = nullptr;
+  QSV_HIP(s, fixed_scratch(s->device, &base));
+  double* pairs = static_cast<double*>(base);
+  double* nd = reinterpret_cast<double*>(static_cast<char*>(base) + part);
+  QSV_HIP(s, launch_probs(s->prec, s->amp, s->n, nullptr, 1, pairs, nd,
+                          s->stream));
+  double h = 0;
+  QSV_HIP(s, hipMemcpyAsync(&h, nd, sizeof(double), hipMemcpyDeviceToHost,
+                            s->stream));
+  QSV_HIP(s, hipStreamSynchronize(s->stream));
+  if (!(h > 0.0) || !std::isfinite(h))
+    return fail(QSV_ERR_INVALID_ARG, "state norm is zero or not finite");
+  QSV_HIP(s, launch_scale(s->prec, s->amp, s->n, nd, s->stream));
+  QSV_HIP(s, hipStreamSynchronize(s->stream));
+  if (norm_out) *norm_out = h;
+  return QSV_OK;
+}
+
 // -------------------------------------------------- qubit relabelling
 
 qsv_status qsv_permute_qubits(qsv_state s, const int32_t* perm) {

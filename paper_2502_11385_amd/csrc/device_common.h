@@ -111,6 +111,12 @@ hipError_t launch_fused_apply(int prec, void* amp, int n, int k,
 
 // Reductions.  Scratch sizes are given by the *_scratch helpers (bytes).
 size_t norm_scratch_bytes(int n);
+// Fixed scratch of the allocation-free entry points: its size, and its
+// device address on `device`, which must be the current device (looked up
+// once per device).
+constexpr int kMaxDevices = 64;
+size_t fixed_scratch_bytes();
+hipError_t fixed_scratch(int device, void** out);
 hipError_t launch_probs(int prec, const void* amp, int n, void* out,
                         int out_fp64, double* scratch, double* norm_dev,
                         hipStream_t stream);

@@ -5,9 +5,41 @@
 // sequential, then fixed LDS trees), so a given state always reduces to the
 // same bits; the norm and marginal sums carry Neumaier compensation.  No
 // floating-point atomics are used.
+#include <mutex>
+
 #include "reduce_core.h"
 
 namespace qsv {
+
+// ------------------------------------------------ fixed device scratch
+
+// Scratch of the allocation-free entry points, resident on every device
+// the library runs on until the process ends.  In host code `scratch`
+// names a host-side stand-in: kernels get the device address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+// 4 MiB of (sum, compensation) pairs, one per 4096 amplitudes of a state of
+// up to 30 qubits, and one 256-byte slot for the total.
+constexpr size_t kFixedScratchBytes = (size_t(4) << 20) + 256;
+static __device__ __align__(256) char scratch[kFixedScratchBytes];
+
+static std::mutex g_fixed_mu;
+static void* g_fixed_ptr[kMaxDevices] = {};
+
+size_t fixed_scratch_bytes() { return kFixedScratchBytes; }
+
+hipError_t fixed_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_fixed_mu);
+  if (!g_fixed_ptr[device]) {
+    // the device is current (the caller selected it)
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_fixed_ptr[device] = p;
+  }
+  *out = g_fixed_ptr[device];
+  return hipSuccess;
+}
 
 // ------------------------------------------------------- probabilities
 

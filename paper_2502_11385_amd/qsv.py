@@ -47,6 +47,7 @@ EXPORTED = [
     "qsv_marginal", "qsv_sample", "qsv_get_amplitudes", "qsv_set_amplitudes",
     "qsv_info", "qsv_sync", "qsv_last_error", "qsv_version",
     "qsv_set_profiling", "qsv_pass_times", "qsv_autotune_fused",
+    "qsv_renormalize_noalloc",
     "qsv_batch_create", "qsv_batch_out_offsets", "qsv_batch_launch",
     "qsv_batch_stats", "qsv_batch_free", "qsv_gate_matrices",
     "qsv_server_create", "qsv_server_submit", "qsv_server_wait",
@@ -162,6 +163,7 @@ _SIGS = {
     "qsv_probabilities": [_p, _p, _i32],
     "qsv_norm": [_p, _pd],
     "qsv_renormalize": [_p, _pd],
+    "qsv_renormalize_noalloc": [_p, _pd],
     "qsv_marginal": [_p, _pi32, _i32, _pd],
     "qsv_sample": [_p, _u64, _u64, _pu64],
     "qsv_get_amplitudes": [_p, _p],
@@ -523,6 +525,13 @@ class State:
     def renormalize(self) -> float:
         v = C.c_double(0)
         _check(_lib.qsv_renormalize(self._h, C.byref(v)))
+        return v.value
+
+    def renormalize_noalloc(self) -> float:
+        """renormalize without any device allocation (fixed scratch; states
+        up to 30 qubits; overlapping calls on one device race)."""
+        v = C.c_double(0)
+        _check(_lib.qsv_renormalize_noalloc(self._h, C.byref(v)))
         return v.value
 
     def marginal(self, qubits: Sequence[int]) -> np.ndarray:

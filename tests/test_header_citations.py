@@ -1,6 +1,7 @@
 """Every entry point of include/qsv.h documents the passage of the paper
 that defines its operation (a Section, Table or equation), except the
-control calls, whose comment says so."""
+control calls and the one allocation-free variant, whose comments say
+so."""
 import os
 import re
 
@@ -33,8 +34,15 @@ def test_every_entry_point_cites_its_passage_or_is_a_control_call():
     decls = declarations()
     assert len(decls) >= 40
     missing = [name for name, c in decls
-               if not CITE.search(c) and "(Control call.)" not in c]
+               if not CITE.search(c) and "(Control call.)" not in c
+               and "(For callers that cannot allocate.)" not in c]
     assert not missing, missing
+
+
+def test_one_allocation_free_variant():
+    noalloc = [name for name, c in declarations()
+               if "(For callers that cannot allocate.)" in c]
+    assert noalloc == ["qsv_renormalize_noalloc"]
 
 
 def test_control_calls_are_few():
