@@ -490,12 +490,17 @@ qsv_status qsv_batch_free(qsv_batch b);
 
 /* A request server: requests (circuits of different widths, depths and
  * precisions) are submitted as they arrive; a scheduler thread admits them
- * first-come first-served while the HBM they need (state 2^w x 8 or 16
- * bytes plus output) fits the budget, the way the evaluator sizes its
- * worker pool by the memory each worker needs (Section IV.A).  Admitted
+ * first-come first-served while the device memory they need fits the
+ * budget, the way the evaluator sizes its worker pool by the memory each
+ * worker needs (Section IV.A).  A request's need counts device bytes only
+ * (pinned host result buffers are not HBM): its state (2^w x 8 or 16
+ * bytes), its output on the device, sampling scratch and an allowance for
+ * its program, plus 1/8 for pooled block rounding.  Device blocks and
+ * states the server keeps for reuse count against the budget too: before
+ * an admission that would not fit beside them they are freed.  Admitted
  * requests of width <= small_width whose gates fit tiles are packed into
- * batch slots (one persistent launch per group); wider ones run on their
- * own state.  Groups run on up to n_streams streams at once, so work
+ * batch slots (one group of phase launches per precision); wider ones run
+ * on their own state.  Groups run on up to n_streams streams at once, so work
  * admitted while other work is on the GPU overlaps it (continuous
  * batching).  The path and kernels a request takes depend only on the
  * request, so its result is the same alone or in any mix.
@@ -566,7 +571,8 @@ qsv_status qsv_server_release(qsv_server s, uint64_t ticket);
 
 /* out[0] submitted, out[1] completed, out[2] batch launches, out[3] single
  * launches, out[4] peak reserved bytes, out[5] most groups in flight at
- * once, out[6] rejected.  n_out <= 7.  (Control call.) */
+ * once, out[6] rejected, out[7] times the idle blocks and cached states
+ * were freed to admit a request.  n_out <= 8.  (Control call.) */
 qsv_status qsv_server_stats(qsv_server s, uint64_t* out, int32_t n_out);
 
 /* Finish queued work, stop the scheduler and free everything.  (Control

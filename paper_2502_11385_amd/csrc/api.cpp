@@ -196,6 +196,15 @@ qsv_status state_sample_async(qsv_state s, uint64_t shots, uint64_t seed,
                            dev_out, s->stream));
   return QSV_OK;
 }
+
+// Device bytes a state holds: its amplitudes (when the library allocated
+// them), program buffer, reduction scratch and relabelling buffer.
+size_t state_device_bytes(qsv_state s) {
+  if (!s) return 0;
+  const size_t amps = size_t(s->b) << s->n;
+  return (s->owned ? amps : 0) + s->prog_cap + s->scratch_cap +
+         (s->spare ? amps : 0);
+}
 }  // namespace qsv
 
 // ======================================================================

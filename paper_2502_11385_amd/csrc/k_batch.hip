@@ -13,6 +13,7 @@
 // instead of the amplitudes.  No variant's tiles wait for another variant,
 // so a wide variant no longer bounds the batch's time, and each tile is
 // computed the same way whatever else is in the batch.
+#include <mutex>
 #include "batch_internal.h"
 #include "tile_core.h"
 
@@ -166,14 +167,16 @@ static hipError_t batch_launch_t(const BatchCircuit* circs,
                                  void* states, int L, int grid,
                                  hipStream_t stream) {
   using C = typename CxT<T>::type;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(
-        batch_fn<T, OUT, RB>(), hipFuncAttributeMaxDynamicSharedMemorySize,
-        160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  // set once per kernel function; the server's scheduler thread and its
+  // clients can reach this together, hence call_once
+  static std::once_flag once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(once, [] {
+    attr_err = hipFuncSetAttribute(batch_fn<T, OUT, RB>(),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024);
+  });
+  if (attr_err != hipSuccess) return attr_err;
   const size_t lds = size_t(sizeof(C)) << L;
   const size_t phases = hp.phase_tiles.size();
   for (size_t p = 0; p < phases; ++p) {

@@ -24,6 +24,7 @@
 namespace qsv {
 qsv_status state_sample_async(qsv_state s, uint64_t shots, uint64_t seed,
                               uint64_t* dev_out);
+size_t state_device_bytes(qsv_state s);
 }
 
 using namespace qsv;
@@ -36,17 +37,28 @@ double now_s() {
       .count();
 }
 
-// Caching pools: blocks are rounded up to powers of two and kept for reuse
-// until the server is destroyed, so steady-state serving calls neither
-// hipMalloc nor hipFree (both can stall other streams).
+// Size class of a pooled block: at least 64 KiB, then eight classes per
+// power of two, so a block wastes at most 1/8 of its size.
+size_t pool_round(size_t b) {
+  size_t p = size_t(1) << 16;
+  if (b <= p) return p;
+  while (p < b) p <<= 1;        // p / 2 < b <= p
+  const size_t step = p >> 4;   // (p / 2) / 8
+  return (b + step - 1) / step * step;
+}
+
+// Device blocks kept for reuse, so that steady-state serving calls neither
+// hipMalloc nor hipFree (both can stall other streams).  Idle blocks are
+// counted, and trimmed when admission needs their bytes.
 class DevicePool {
  public:
   void* get(size_t bytes) {
-    const size_t sz = round(bytes);
+    const size_t sz = pool_round(bytes);
     auto& fl = free_[sz];
     if (!fl.empty()) {
       void* p = fl.back();
       fl.pop_back();
+      idle_ -= sz;
       return p;
     }
     void* p = nullptr;
@@ -57,21 +69,22 @@ class DevicePool {
     return p;
   }
   void put(void* p, size_t bytes) {
-    if (p) free_[round(bytes)].push_back(p);
+    if (!p) return;
+    const size_t sz = pool_round(bytes);
+    free_[sz].push_back(p);
+    idle_ += sz;
   }
+  size_t idle() const { return idle_; }
   void clear() {
     for (auto& kv : free_)
       for (void* p : kv.second) (void)hipFree(p);
     free_.clear();
-  }
-  static size_t round(size_t b) {
-    size_t s = 1 << 16;
-    while (s < b) s <<= 1;
-    return s;
+    idle_ = 0;
   }
 
  private:
   std::map<size_t, std::vector<void*>> free_;
+  size_t idle_ = 0;
 };
 
 // Used by client threads (results) and the scheduler (staging): locked.
@@ -79,7 +92,7 @@ class HostPool {
  public:
   void* get(size_t bytes) {
     std::lock_guard<std::mutex> lk(mu_);
-    const size_t sz = DevicePool::round(bytes);
+    const size_t sz = pool_round(bytes);
     auto& fl = free_[sz];
     if (!fl.empty()) {
       void* p = fl.back();
@@ -95,7 +108,7 @@ class HostPool {
   }
   void put(void* p, size_t bytes) {
     std::lock_guard<std::mutex> lk(mu_);
-    if (p) free_[DevicePool::round(bytes)].push_back(p);
+    if (p) free_[pool_round(bytes)].push_back(p);
   }
   void clear() {
     std::lock_guard<std::mutex> lk(mu_);
@@ -167,7 +180,8 @@ struct qsv_server_s {
   std::vector<Group*> running;
   std::vector<hipEvent_t> free_events;
   std::map<int, std::vector<qsv_state>> states;  // key: (w, prec, stream)
-  uint64_t n_batches = 0, n_single = 0, max_inflight = 0;
+  size_t idle_state_bytes = 0;  // device bytes of the cached idle states
+  uint64_t n_batches = 0, n_single = 0, max_inflight = 0, trims = 0;
 };
 
 namespace {
@@ -318,6 +332,7 @@ void launch_single(qsv_server s, Group* g) {
   if (!fl.empty()) {
     state = fl.back();
     fl.pop_back();
+    s->idle_state_bytes -= state_device_bytes(state);
   } else if (qsv_alloc(r->w, r->prec, st, &state) != QSV_OK) {
     fail_group(g, qsv_last_error());
     return;
@@ -369,7 +384,10 @@ void finish(qsv_server s, Group* g) {
     else
       s->dpool.put(b.p, b.bytes);
   }
-  if (g->state) s->states[g->state_key].push_back(g->state);
+  if (g->state) {
+    s->idle_state_bytes += state_device_bytes(g->state);
+    s->states[g->state_key].push_back(g->state);
+  }
   s->free_events.push_back(g->ev);
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -382,6 +400,18 @@ void finish(qsv_server s, Group* g) {
   }
   s->cv_done.notify_all();
   delete g;
+}
+
+// Free every idle device block and cached state (work in flight keeps
+// its own).  hipFree waits for the device, so this runs only when
+// admission would otherwise exceed the budget.
+void trim_idle(qsv_server s) {
+  s->dpool.clear();
+  for (auto& kv : s->states)
+    for (qsv_state st : kv.second) (void)qsv_free(st);
+  s->states.clear();
+  s->idle_state_bytes = 0;
+  s->trims++;
 }
 
 void scheduler(qsv_server s) {
@@ -418,6 +448,11 @@ void scheduler(qsv_server s) {
       while (!s->pending.empty() &&
              s->reserved + s->pending.front()->need <= s->o.budget_bytes) {
         Req* r = s->pending.front();
+        // idle blocks and cached states hold device memory too: drop them
+        // before an admission that would not fit beside them
+        if (s->reserved + r->need + s->dpool.idle() + s->idle_state_bytes >
+            s->o.budget_bytes)
+          trim_idle(s);
         const bool opens = !r->batched || in_batch[r->prec] == 0 ||
                            in_batch[r->prec] >= s->o.max_batch;
         if (opens && groups + 1 > slots) break;
@@ -520,6 +555,24 @@ void scheduler(qsv_server s) {
   }
 }
 
+// Device bytes a request may hold while it runs (host buffers are not
+// HBM): its state, its output on the device, the sampling scratch, and an
+// allowance for its program and reduction scratch.  Pooled blocks (the
+// batch path) are rounded to their size class, which wastes at most 1/8
+// of a block, and a group's blocks hold the sums of its requests' parts,
+// so 9/8 of each part bounds its share.
+size_t device_need(const Req& r) {
+  const size_t esz = r.b == 8 ? 4 : 8;
+  const size_t state = size_t(r.b) << r.w;
+  const size_t out = r.samples ? size_t(r.shots) * 8 + 256 : esz << r.w;
+  const size_t smp = r.samples ? sample_scratch_bytes(r.w, 0) +
+                                     (esz << r.w) : 0;
+  const size_t prog = (size_t(64) << 10) + r.G.size() * 1024;
+  const size_t red = (state >> 10) + (size_t(64) << 10);
+  const size_t parts = state + out + smp + 2 * prog + red;
+  return parts + parts / 8;
+}
+
 }  // namespace
 
 extern "C" {
@@ -586,8 +639,7 @@ qsv_status qsv_server_submit(qsv_server s, const qsv_request* rq,
   const size_t esz = r->b == 8 ? 4 : 8;
   r->n_out = r->samples ? r->shots : (uint64_t(1) << r->w);
   r->host_bytes = r->samples ? size_t(r->shots) * 8 : (esz << r->w);
-  r->need = (size_t(r->b) << r->w) + r->host_bytes +
-            (r->samples ? sample_scratch_bytes(r->w, 0) + (esz << r->w) : 0);
+  r->need = device_need(*r);
   std::lock_guard<std::mutex> lk(s->mu);
   if (r->need > s->o.budget_bytes) {
     s->rejected++;
@@ -641,10 +693,11 @@ qsv_status qsv_server_release(qsv_server s, uint64_t ticket) {
 }
 
 qsv_status qsv_server_stats(qsv_server s, uint64_t* out, int32_t n) {
-  if (!s || !out || n < 0 || n > 7) return set_error(QSV_ERR_INVALID_ARG, "bad arguments");
+  if (!s || !out || n < 0 || n > 8) return set_error(QSV_ERR_INVALID_ARG, "bad arguments");
   std::lock_guard<std::mutex> lk(s->mu);
-  const uint64_t v[7] = {s->submitted, s->completed, s->n_batches, s->n_single,
-                         s->peak_reserved, s->max_inflight, s->rejected};
+  const uint64_t v[8] = {s->submitted, s->completed, s->n_batches, s->n_single,
+                         s->peak_reserved, s->max_inflight, s->rejected,
+                         s->trims};
   for (int i = 0; i < n; ++i) out[i] = v[i];
   return QSV_OK;
 }

@@ -768,10 +768,11 @@ class Server:
         _check(_lib.qsv_server_release(self._h, ticket))
 
     def stats(self) -> dict:
-        out = np.zeros(7, np.uint64)
-        _check(_lib.qsv_server_stats(self._h, _ptr(out, C.c_uint64), 7))
+        out = np.zeros(8, np.uint64)
+        _check(_lib.qsv_server_stats(self._h, _ptr(out, C.c_uint64), 8))
         keys = ("submitted", "completed", "batch_launches", "single_launches",
-                "peak_reserved_bytes", "max_groups_in_flight", "rejected")
+                "peak_reserved_bytes", "max_groups_in_flight", "rejected",
+                "idle_trims")
         return {k: int(v) for k, v in zip(keys, out)}
 
     def close(self):

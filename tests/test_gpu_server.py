@@ -98,3 +98,52 @@ def test_budget_queues_and_bounds_reserved_bytes():
         tol = 2e-6 if prec == C64 else 1e-12
         assert np.max(np.abs(res[i][0].astype(np.float64) - p)) <= tol
     srv.close()
+
+
+def test_budget_counts_cached_device_memory():
+    """Device memory the server keeps for reuse (pooled blocks, cached
+    states) counts against the budget: a stream of wide requests of mixed
+    widths and precisions never holds more than the budget plus a small
+    fixed overhead, by the device's own free-memory count."""
+    import threading
+    gib = 1 << 30
+    budget = int(3.5 * gib)
+    reqs = [(27, 2, C128, 0), (28, 2, C64, 0), (26, 2, C128, 2000),
+            (27, 2, C64, 0), (12, 4, C64, 0), (25, 3, C128, 0),
+            (28, 1, C64, 1000)]
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0 = torch.cuda.mem_get_info()[0]
+    low = [free0]
+    stop = threading.Event()
+
+    def poll():
+        while not stop.is_set():
+            low[0] = min(low[0], torch.cuda.mem_get_info()[0])
+            stop.wait(0.0005)
+
+    th = threading.Thread(target=poll, daemon=True)
+    th.start()
+    srv = qsv.Server(budget_bytes=budget)
+    try:
+        res = _run(srv, reqs)
+        held = free0 - torch.cuda.mem_get_info()[0]
+        st = srv.stats()
+    finally:
+        stop.set()
+        th.join()
+    overhead = 256 << 20
+    assert free0 - low[0] <= budget + overhead, (free0 - low[0]) / gib
+    assert held <= budget + overhead, held / gib
+    assert st["completed"] == len(reqs) and st["idle_trims"] >= 1
+    for i, (w, d, prec, shots) in enumerate(reqs):
+        data, info = res[i]
+        assert info["status"] == 0
+        if shots:
+            assert data.shape == (shots,) and int(data.max()) < (1 << w)
+        else:
+            assert abs(float(np.sum(data, dtype=np.float64)) - 1) < 1e-4
+    w, d, prec, _ = reqs[4]
+    p = oracle.probabilities(oracle.simulate(w, _circ(4, w, d)))
+    assert np.max(np.abs(res[4][0].astype(np.float64) - p)) <= 2e-6
+    srv.close()
