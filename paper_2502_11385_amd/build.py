@@ -5,6 +5,7 @@ Usage: python -m paper_2502_11385_amd.build   (or __graft_entry__.build())
 from __future__ import annotations
 
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -44,17 +45,42 @@ UNSTRUCTURED = ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]
 TILE_SOURCES = ("k_tile.hip", "k_batch.hip")
 
 
+# The compiler's per-kernel resource report (registers, scratch, spills,
+# occupancy) of each device source, kept beside its object file.
+RESOURCES = ["-Rpass-analysis=kernel-resource-usage"]
+_REMARK = re.compile(r"remark:\s+(Function Name|VGPRs|AGPRs|"
+                     r"ScratchSize \[bytes/lane\]|Occupancy \[waves/SIMD\]|"
+                     r"VGPRs Spill|SGPRs Spill|LDS Size \[bytes/block\]): "
+                     r"(\S+)")
+
+
+def resource_table(stderr: str) -> str:
+    """One line per kernel: name, then key=value fields of the report."""
+    rows, cur = [], None
+    for m in _REMARK.finditer(stderr):
+        key, val = m.group(1), m.group(2)
+        if key == "Function Name":
+            cur = [val]
+            rows.append(cur)
+        elif cur is not None:
+            cur.append(f"{key.split(' [')[0].replace(' ', '_')}={val}")
+    return "".join(" ".join(r) + "\n" for r in rows)
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC] + COMMON + DEVICE
     if src.endswith(".hip"):
-        cmd += ["-x", "hip"] + NO_SINK
+        cmd += ["-x", "hip"] + NO_SINK + RESOURCES
         if src in TILE_SOURCES:
             cmd += UNSTRUCTURED
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+    if src.endswith(".hip"):
+        with open(os.path.splitext(obj)[0] + ".resources.txt", "w") as f:
+            f.write(resource_table(r.stderr))
     return obj
 
 

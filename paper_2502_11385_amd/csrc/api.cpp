@@ -353,9 +353,10 @@ static void block_matrix(const HostGate& g, int32_t* q,
     }
 }
 
-// Gates that take the matrix-core path when run on their own.
+// Gates that take the matrix-core path when run on their own (controls
+// restrict the groups the kernel visits).
 static bool block_gate(const HostGate& g) {
-  return !g.diagonal && g.k >= 4 && g.c == 0;
+  return !g.diagonal && g.k >= 4;
 }
 
 qsv_status qsv_apply_gate(qsv_state s, const int32_t* targets, int32_t k,
@@ -379,8 +380,9 @@ qsv_status qsv_apply_gate(qsv_state s, const int32_t* targets, int32_t k,
   if (g.diagonal) {
     QSV_HIP(s, launch_diag(s->prec, s->amp, s->n, g, s->stream));
   } else if (block_gate(g)) {
-    // 4-5 targets without controls: the matrix-core block kernel of the
-    // fused plans (the matrix rounded once to FP32 for complex64)
+    // 4-5 targets: the matrix-core block kernel of the fused plans (the
+    // matrix rounded once to FP32 for complex64), over the groups whose
+    // control qubits are 1
     int32_t q[kMaxK];
     std::vector<double> mp;
     block_matrix(g, q, &mp);
@@ -392,7 +394,7 @@ qsv_status qsv_apply_gate(qsv_state s, const int32_t* targets, int32_t k,
       return st;
     }
     QSV_HIP(s, launch_fused_apply(s->prec, s->amp, s->n, g.k, q, s->prog_dev,
-                                  s->stream));
+                                  g.cmask, s->stream));
   } else if (g.k <= 2) {
     QSV_HIP(s, launch_dense(s->prec, s->amp, s->n, g, nullptr, s->stream));
   } else {
@@ -524,6 +526,7 @@ static qsv_status apply_fused_impl(qsv_state s, const qsv_circuit* circ,
         std::vector<double> mp;
         FusedBlock fb = {};
         fb.k = g.k;
+        fb.cmask = g.cmask;
         block_matrix(g, fb.q, &mp);
         fb.u64_offset = int64_t(mats.size());
         fb.u32_offset = int64_t(plain32.size());
@@ -720,7 +723,7 @@ static qsv_status apply_fused_impl(qsv_state s, const qsv_circuit* circ,
                             ? static_cast<const void*>(d_m32 + pb.u32_offset)
                             : static_cast<const void*>(d_m64 + pb.u64_offset);
         QSV_HIP(s, launch_fused_apply(s->prec, s->amp, n, pb.k, pb.q, u,
-                                      s->stream));
+                                      pb.cmask, s->stream));
       } else
         QSV_HIP(s, launch_dense(s->prec, s->amp, n, g,
                                 plain_moff[pi] >= 0 ? d_m64 + plain_moff[pi]
@@ -732,7 +735,7 @@ static qsv_status apply_fused_impl(qsv_state s, const qsv_circuit* circ,
                           ? static_cast<const void*>(d_m32 + fb.u32_offset)
                           : static_cast<const void*>(d_m64 + fb.u64_offset);
       QSV_HIP(s, launch_fused_apply(s->prec, s->amp, n, fb.k, fb.q, u,
-                                    s->stream));
+                                    fb.cmask, s->stream));
     }
     if (s->profiling)
       QSV_HIP(s, hipEventRecord(s->evs[2 * pi + 1], s->stream));

@@ -104,10 +104,11 @@ hipError_t launch_fused_build(const FusedBlock* blocks, int n_blocks,
                               const FusedGate* gates, double* mats64,
                               float* mats32, hipStream_t stream);
 // Apply one fused block of width k on qubits q (host copy) with the device
-// matrix u (FP64 for c128, FP32 for c64).
+// matrix u (FP64 for c128, FP32 for c64), where every qubit of cmask is 1
+// (k >= 4 when cmask is not 0).
 hipError_t launch_fused_apply(int prec, void* amp, int n, int k,
                               const int32_t* q, const void* u,
-                              hipStream_t stream);
+                              uint64_t cmask, hipStream_t stream);
 
 // Reductions.  Scratch sizes are given by the *_scratch helpers (bytes).
 size_t norm_scratch_bytes(int n);

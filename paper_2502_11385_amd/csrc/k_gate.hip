@@ -134,8 +134,6 @@ static void dense_dispatch(T*, void* amp, int k, unsigned blocks,
         dense_kernel<T, 2, false><<<blocks, 256, 0, stream>>>(a, args);
       break;
     case 3: dense_kernel<T, 3, true><<<blocks, 256, 0, stream>>>(a, args); break;
-    case 4: dense_kernel<T, 4, true><<<blocks, 256, 0, stream>>>(a, args); break;
-    case 5: dense_kernel<T, 5, true><<<blocks, 256, 0, stream>>>(a, args); break;
   }
 }
 
@@ -148,6 +146,8 @@ static void sorted_positions(uint64_t mask, int32_t* pos, int32_t* npos) {
 
 hipError_t launch_dense(int prec, void* amp, int n, const HostGate& g,
                         const double* dev_matrix, hipStream_t stream) {
+  // 4-5 targets run on the matrix cores (launch_fused_apply)
+  if (g.k > 3) return hipErrorInvalidValue;
   DenseArgs args = {};
   args.n_groups = uint64_t(1) << (n - g.k - g.c);
   args.cmask = g.cmask;
@@ -172,7 +172,7 @@ hipError_t launch_dense(int prec, void* amp, int n, const HostGate& g,
 hipError_t launch_dense_dev(int prec, void* amp, int n, int k,
                             const int32_t* q, const double* dev_matrix,
                             hipStream_t stream) {
-  if (!dev_matrix || k < 1 || k > kMaxK) return hipErrorInvalidValue;
+  if (!dev_matrix || k < 1 || k > 3) return hipErrorInvalidValue;
   DenseArgs args = {};
   args.n_groups = uint64_t(1) << (n - k);
   uint64_t mask = 0;

@@ -188,7 +188,7 @@ struct alignas(16) TilePass {
   int32_t L;
   int32_t nseg;
   int32_t seg_begin;
-  int32_t flags;  // kPassLane32 | kPassSpread | kPassOutputs | kPassOutputs
+  int32_t flags;  // kPassLane32 | kPassSpread | kPassOutputs
   int32_t q[16];
   int32_t out_spec;  // kPassOutputs: byte offset from this record
   int32_t pad_[3];
@@ -214,6 +214,7 @@ struct alignas(16) FusedBlock {
   int64_t u64_offset;  // FP64 product, 2^k x 2^k complex (in doubles)
   int64_t u32_offset;  // the same rounded once to FP32 (in floats)
   int32_t q[8];
+  uint64_t cmask;      // control qubits (all must be 1); 0 for products
 };
 
 // One variant of a batch: its width, its tile passes (all its gates run in
