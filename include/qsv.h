@@ -54,7 +54,9 @@ typedef enum {
   QSV_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed */
   QSV_ERR_DEVICE = 3,        /* a HIP call or kernel failed */
   QSV_ERR_UNSUPPORTED = 4,   /* unknown precision, gate or strategy */
-  QSV_ERR_BUDGET = 5         /* request larger than an admission budget */
+  QSV_ERR_BUDGET = 5,        /* request larger than an admission budget */
+  QSV_ERR_CANCELLED = 6,     /* a queued request was cancelled */
+  QSV_ERR_TIMEOUT = 7        /* a wait ended before the request finished */
 } qsv_status;
 
 typedef enum { QSV_C64 = 1, QSV_C128 = 2 } qsv_precision;
@@ -284,6 +286,16 @@ qsv_status qsv_plan_describe(const qsv_circuit* circ, int32_t n_qubits,
 qsv_status qsv_plan_program_stats(const qsv_circuit* circ, int32_t n_qubits,
                                   int32_t prec, const qsv_fuse_opts* opts,
                                   uint64_t* out, int32_t n_out);
+
+/* Testing aid for the failure paths (Control call.): kind 1 makes the
+ * next `count` device allocations of the library (states, program
+ * buffers, scratch) fail as out of memory, without allocating; kind 2 makes
+ * the next `count` device calls made for a state fail as device errors,
+ * without making them, so that the state turns failed (every later call on
+ * it returns QSV_ERR_DEVICE) while other states are unaffected.  count 0
+ * clears the kind.  Process-wide.  QSV_ERR_INVALID_ARG for another kind or
+ * a negative count. */
+qsv_status qsv_debug_inject(int32_t kind, int32_t count);
 
 /* Testing aid (host only, no device work): plan the circuit with the
  * tiled strategy (Section III.B's cache blocking) for n_qubits <= 16,
@@ -565,6 +577,21 @@ qsv_status qsv_server_submit(qsv_server s, const qsv_request* req,
  * QSV_ERR_INVALID_ARG for an unknown ticket; the request's own status is
  * in out->status. */
 qsv_status qsv_server_wait(qsv_server s, uint64_t ticket, qsv_result* out);
+
+/* qsv_server_wait with a time limit: returns QSV_ERR_TIMEOUT if the
+ * request has not finished within timeout_s seconds (it stays queued or
+ * running and can be waited for again), else as qsv_server_wait (the
+ * probability vector or shots of Sections III.A / IV.A).  Errors:
+ * QSV_ERR_INVALID_ARG for an unknown ticket or a negative or non-finite
+ * timeout. */
+qsv_status qsv_server_wait_timeout(qsv_server s, uint64_t ticket,
+                                   double timeout_s, qsv_result* out);
+
+/* Withdraw a request that is still queued (not yet admitted to the
+ * device): it finishes with status QSV_ERR_CANCELLED (qsv_server_wait
+ * reports it) and nothing of it runs.  QSV_ERR_INVALID_ARG for an unknown
+ * ticket or a request already admitted or finished.  (Control call.) */
+qsv_status qsv_server_cancel(qsv_server s, uint64_t ticket);
 
 /* Free the ticket's result buffers.  (Control call.) */
 qsv_status qsv_server_release(qsv_server s, uint64_t ticket);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -64,10 +65,28 @@ qsv_status device_fail(qsv_state s, hipError_t e, const char* what) {
   return e == hipErrorOutOfMemory ? QSV_ERR_OUT_OF_MEMORY : QSV_ERR_DEVICE;
 }
 
-#define QSV_HIP(s, call)                                 \
-  do {                                                   \
-    hipError_t e_ = (call);                              \
-    if (e_ != hipSuccess) return device_fail(s, e_, #call); \
+// Failure injection (qsv_debug_inject): counts of allocations and of
+// state device calls still to fail.
+std::atomic<int> g_inject_alloc{0}, g_inject_call{0};
+
+bool take_injected(std::atomic<int>& c) {
+  int v = c.load();
+  while (v > 0)
+    if (c.compare_exchange_weak(v, v - 1)) return true;
+  return false;
+}
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+  if (take_injected(g_inject_alloc)) return hipErrorOutOfMemory;
+  return hipMalloc(p, bytes);
+}
+
+#define QSV_HIP(s, call)                                             \
+  do {                                                               \
+    if (take_injected(g_inject_call))                                \
+      return device_fail(s, hipErrorLaunchFailure, "injected: " #call); \
+    hipError_t e_ = (call);                                          \
+    if (e_ != hipSuccess) return device_fail(s, e_, #call);          \
   } while (0)
 
 qsv_status check_state(qsv_state s) {
@@ -93,7 +112,7 @@ qsv_status ensure_scratch(qsv_state s, size_t bytes) {
   s->scratch = nullptr;
   s->scratch_cap = 0;
   size_t cap = std::max(bytes, size_t(1) << 16);
-  hipError_t e = hipMalloc(&s->scratch, cap);
+  hipError_t e = dev_malloc(reinterpret_cast<void**>(&s->scratch), cap);
   if (e != hipSuccess) {
     s->scratch = nullptr;
     (void)hipGetLastError();
@@ -115,7 +134,7 @@ qsv_status upload(qsv_state s, const void* data, size_t bytes) {
     s->prog_dev = nullptr;
     s->prog_cap = 0;
     size_t cap = std::max(bytes, std::max(size_t(1) << 16, 2 * old));
-    hipError_t e = hipMalloc(&s->prog_dev, cap);
+    hipError_t e = dev_malloc(reinterpret_cast<void**>(&s->prog_dev), cap);
     if (e != hipSuccess) {
       s->prog_dev = nullptr;
       (void)hipGetLastError();
@@ -215,6 +234,17 @@ const char* qsv_last_error(void) { return g_err.c_str(); }
 
 const char* qsv_version(void) { return "qsv 0.1 (gfx950)"; }
 
+qsv_status qsv_debug_inject(int32_t kind, int32_t count) {
+  if (count < 0) return fail(QSV_ERR_INVALID_ARG, "negative count");
+  if (kind == 1)
+    g_inject_alloc.store(count);
+  else if (kind == 2)
+    g_inject_call.store(count);
+  else
+    return fail(QSV_ERR_INVALID_ARG, "kind must be 1 or 2");
+  return QSV_OK;
+}
+
 qsv_status qsv_alloc(int32_t n, int32_t prec, void* stream, qsv_state* out) {
   if (!out) return fail(QSV_ERR_INVALID_ARG, "null output pointer");
   *out = nullptr;
@@ -227,7 +257,7 @@ qsv_status qsv_alloc(int32_t n, int32_t prec, void* stream, qsv_state* out) {
   if (e != hipSuccess) return device_fail(nullptr, e, "hipGetDevice");
   const size_t bytes = size_t(bytes_of(prec)) << n;
   void* p = nullptr;
-  e = hipMalloc(&p, bytes);
+  e = dev_malloc(&p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(QSV_ERR_OUT_OF_MEMORY,
@@ -1486,7 +1516,7 @@ qsv_status qsv_permute_qubits(qsv_state s, const int32_t* perm) {
   const size_t bytes = size_t(s->b) << n;
   if (!s->spare) {
     QSV_HIP(s, hipStreamSynchronize(s->stream));
-    hipError_t e = hipMalloc(&s->spare, bytes);
+    hipError_t e = dev_malloc(&s->spare, bytes);
     if (e != hipSuccess) {
       s->spare = nullptr;
       (void)hipGetLastError();

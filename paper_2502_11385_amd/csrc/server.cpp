@@ -10,6 +10,7 @@
 // is admitted and launched while earlier work is still on the device.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -182,6 +183,7 @@ struct qsv_server_s {
   std::map<int, std::vector<qsv_state>> states;  // key: (w, prec, stream)
   size_t idle_state_bytes = 0;  // device bytes of the cached idle states
   uint64_t n_batches = 0, n_single = 0, max_inflight = 0, trims = 0;
+  uint64_t cancelled = 0;  // under mu
 };
 
 namespace {
@@ -656,13 +658,20 @@ qsv_status qsv_server_submit(qsv_server s, const qsv_request* rq,
   return QSV_OK;
 }
 
-qsv_status qsv_server_wait(qsv_server s, uint64_t ticket, qsv_result* out) {
+static qsv_status wait_impl(qsv_server s, uint64_t ticket, double timeout_s,
+                            qsv_result* out) {
   if (!s || !out) return set_error(QSV_ERR_INVALID_ARG, "null argument");
   std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->all.find(ticket);
   if (it == s->all.end()) return set_error(QSV_ERR_INVALID_ARG, "unknown ticket");
   Req* r = it->second;
-  s->cv_done.wait(lk, [r] { return r->done; });
+  if (timeout_s < 0) {
+    s->cv_done.wait(lk, [r] { return r->done; });
+  } else if (!s->cv_done.wait_for(
+                 lk, std::chrono::duration<double>(timeout_s),
+                 [r] { return r->done; })) {
+    return set_error(QSV_ERR_TIMEOUT, "request not finished within the timeout");
+  }
   out->status = r->status;
   out->width = r->w;
   out->prec = r->prec;
@@ -676,6 +685,41 @@ qsv_status qsv_server_wait(qsv_server s, uint64_t ticket, qsv_result* out) {
   out->t_start = r->t_start;
   out->t_done = r->t_done;
   if (r->status != QSV_OK) return set_error(qsv_status(r->status), r->err);
+  return QSV_OK;
+}
+
+qsv_status qsv_server_wait(qsv_server s, uint64_t ticket, qsv_result* out) {
+  return wait_impl(s, ticket, -1.0, out);
+}
+
+qsv_status qsv_server_wait_timeout(qsv_server s, uint64_t ticket,
+                                   double timeout_s, qsv_result* out) {
+  if (!(timeout_s >= 0) || !std::isfinite(timeout_s))
+    return set_error(QSV_ERR_INVALID_ARG, "timeout must be finite and >= 0");
+  return wait_impl(s, ticket, timeout_s, out);
+}
+
+qsv_status qsv_server_cancel(qsv_server s, uint64_t ticket) {
+  if (!s) return set_error(QSV_ERR_INVALID_ARG, "null server");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end())
+      return set_error(QSV_ERR_INVALID_ARG, "unknown ticket");
+    Req* r = it->second;
+    auto q = std::find(s->pending.begin(), s->pending.end(), r);
+    if (q == s->pending.end())
+      return set_error(QSV_ERR_INVALID_ARG,
+                       "request already admitted or finished");
+    s->pending.erase(q);
+    r->status = QSV_ERR_CANCELLED;
+    r->err = "request cancelled";
+    r->t_admit = r->t_start = r->t_done = now_s();
+    r->done = true;
+    s->completed++;
+    s->cancelled++;
+  }
+  s->cv_done.notify_all();
   return QSV_OK;
 }
 

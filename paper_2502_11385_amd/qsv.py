@@ -34,6 +34,8 @@ QSV_ERR_OUT_OF_MEMORY = 2
 QSV_ERR_DEVICE = 3
 QSV_ERR_UNSUPPORTED = 4
 QSV_ERR_BUDGET = 5
+QSV_ERR_CANCELLED = 6
+QSV_ERR_TIMEOUT = 7
 QSV_C64 = 1
 QSV_C128 = 2
 PLAN_AUTO, PLAN_PLAIN, PLAN_TILED, PLAN_FUSED = 0, 1, 2, 3
@@ -52,6 +54,7 @@ EXPORTED = [
     "qsv_batch_stats", "qsv_batch_free", "qsv_gate_matrices",
     "qsv_server_create", "qsv_server_submit", "qsv_server_wait",
     "qsv_server_release", "qsv_server_stats", "qsv_server_destroy",
+    "qsv_server_wait_timeout", "qsv_server_cancel", "qsv_debug_inject",
     "qsv_clock", "qsv_debug_emulate_tiled", "qsv_plan_program_stats",
     "qsv_cut_workspace_bytes", "qsv_cut_reconstruct",
     "qsv_top_k", "qsv_expectation_pauli", "qsv_permute_qubits",
@@ -180,6 +183,9 @@ _SIGS = {
     "qsv_server_create": [C.POINTER(qsv_server_opts), C.POINTER(_p)],
     "qsv_server_submit": [_p, C.POINTER(qsv_request), _pu64],
     "qsv_server_wait": [_p, _u64, C.POINTER(qsv_result)],
+    "qsv_server_wait_timeout": [_p, _u64, C.c_double, C.POINTER(qsv_result)],
+    "qsv_server_cancel": [_p, _u64],
+    "qsv_debug_inject": [_i32, _i32],
     "qsv_server_release": [_p, _u64],
     "qsv_server_stats": [_p, _pu64, _i32],
     "qsv_server_destroy": [_p],
@@ -204,6 +210,13 @@ _lib.qsv_version.restype = C.c_char_p
 _lib.qsv_version.argtypes = []
 _lib.qsv_clock.restype = C.c_double
 _lib.qsv_clock.argtypes = []
+
+
+def debug_inject(kind: int, count: int) -> None:
+    """Failure injection for tests: kind 1 = the next `count` device
+    allocations fail, kind 2 = the next `count` device calls made for a
+    state fail (that state turns failed); count 0 clears."""
+    _check(_lib.qsv_debug_inject(int(kind), int(count)))
 
 
 def lib():
@@ -741,11 +754,16 @@ class Server:
         _check(_lib.qsv_server_submit(self._h, C.byref(req), C.byref(t)))
         return t.value
 
-    def wait(self, ticket: int, copy: bool = True):
+    def wait(self, ticket: int, copy: bool = True, timeout=None):
         """(data, info) for a finished request; data is a NumPy copy of the
-        probabilities (float32/float64) or samples (uint64)."""
+        probabilities (float32/float64) or samples (uint64).  With a timeout
+        (seconds), raises QsvError(QSV_ERR_TIMEOUT) if it has not finished."""
         r = qsv_result()
-        st = _lib.qsv_server_wait(self._h, ticket, C.byref(r))
+        if timeout is None:
+            st = _lib.qsv_server_wait(self._h, ticket, C.byref(r))
+        else:
+            st = _lib.qsv_server_wait_timeout(self._h, ticket, float(timeout),
+                                              C.byref(r))
         info = {"status": r.status, "width": r.width, "prec": r.prec,
                 "samples": bool(r.is_samples), "batched": bool(r.batched),
                 "t_submit": r.t_submit, "t_admit": r.t_admit,
@@ -763,6 +781,10 @@ class Server:
             buf = (ct * r.n_out).from_address(r.data)
             data = np.frombuffer(buf, dtype=dt).copy()
         return data, info
+
+    def cancel(self, ticket: int):
+        """Withdraw a request that has not been admitted yet."""
+        _check(_lib.qsv_server_cancel(self._h, ticket))
 
     def release(self, ticket: int):
         _check(_lib.qsv_server_release(self._h, ticket))
