@@ -600,7 +600,7 @@ def plans_leg(qsv, torch, np, circ, n: int) -> dict:
 WIDE = ((34, "c64", 34), (33, "c128", 33))   # (qubits, precision, seed)
 
 
-def wide_leg(qsv, torch, np) -> dict:
+def wide_leg(qsv, torch, np, autotune: bool = True) -> dict:
     """The widest states one GPU holds (128 GiB each): 34 qubits complex64
     and 33 qubits complex128, a QFT ladder on a random basis state followed
     by 10 layered U3+CZ layers, then the marginal of the top 10 qubits and
@@ -615,7 +615,10 @@ def wide_leg(qsv, torch, np) -> dict:
         circ = qsv.Circuit.from_gates(gates)
         s = qsv.State(n, prec, stream=torch.cuda.current_stream())
         s.init_basis(x)
-        best, bms, dms, _ = s.autotune(circ)
+        if autotune:
+            best, bms, dms, _ = s.autotune(circ)
+        else:
+            best, bms, dms = qsv.fuse_opts(), 0.0, 0.0
         s.set_profiling(True)
         tot = 0.0
         for _ in range(2):
@@ -637,7 +640,8 @@ def wide_leg(qsv, torch, np) -> dict:
             "circuit_ms": round(tot, 1),
             "autotuned": dict(_opts_dict(best),
                               tuner_circuit_ms=round(bms, 1),
-                              default_circuit_ms=round(dms, 1)),
+                              default_circuit_ms=round(dms, 1))
+            if autotune else None,
             "mean_pass_GBps": round(st["alg_bytes"] / (tot * 1e-3) / 1e9, 1),
             "tile_TFLOPs": round(st["tile_flops"] / (tile_ms * 1e-3) / 1e12,
                                  2) if tile_ms else None,
@@ -1232,7 +1236,7 @@ def main() -> int:
         out["small"] = small_leg(qsv, torch, np)
     if not a.no_wide:
         _note("wide leg")
-        out["wide"] = wide_leg(qsv, torch, np)
+        out["wide"] = wide_leg(qsv, torch, np, not a.no_autotune)
     if not a.no_cut:
         _note("cut leg")
         out["cut"] = cut_leg(qsv, torch, np, max(1, a.steps))

@@ -36,11 +36,22 @@ struct CxT<double> {
   using type = double2;
 };
 
+// Fused multiply-add of the component type.
+__device__ __forceinline__ float fmac(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+__device__ __forceinline__ double fmac(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+
+// Complex products with their fused multiply-adds written out, so that
+// every kernel rounds them the same way (left to the compiler, contraction
+// can differ between kernels that inline the same code).
 template <typename C>
 __device__ __forceinline__ C cmul(C a, C b) {
   C r;
-  r.x = a.x * b.x - a.y * b.y;
-  r.y = a.x * b.y + a.y * b.x;
+  r.x = fmac(a.x, b.x, -(a.y * b.y));
+  r.y = fmac(a.x, b.y, a.y * b.x);
   return r;
 }
 
@@ -48,8 +59,8 @@ __device__ __forceinline__ C cmul(C a, C b) {
 template <typename C>
 __device__ __forceinline__ C cmul2(C a, C x, C b, C y) {
   C r;
-  r.x = a.x * x.x - a.y * x.y + b.x * y.x - b.y * y.y;
-  r.y = a.x * x.y + a.y * x.x + b.x * y.y + b.y * y.x;
+  r.x = fmac(b.y, -y.y, fmac(b.x, y.x, fmac(a.x, x.x, -(a.y * x.y))));
+  r.y = fmac(b.y, y.x, fmac(b.x, y.y, fmac(a.x, x.y, a.y * x.x)));
   return r;
 }
 

@@ -37,8 +37,10 @@ __device__ __forceinline__ void block_reduce_pair(double& s, double& c, double* 
 
 template <typename C>
 __device__ __forceinline__ double prob_of(C v) {
+  // one rounding order in every kernel that computes it (the fused
+  // multiply-add written out, not left to contraction)
   const double x = double(v.x), y = double(v.y);
-  return x * x + y * y;
+  return __builtin_fma(x, x, y * y);
 }
 
 }  // namespace qsv
