@@ -1261,6 +1261,10 @@ def main() -> int:
         if "batch" in out and cb.get("circuits_per_s"):
             out["batch"]["speedup_vs_oracle_cpu"] = round(
                 out["batch"]["circuits_per_s"] / cb["circuits_per_s"], 1)
+        cp = out["cpu_baseline"].get("batch_pool") or {}
+        if "batch" in out and cp.get("circuits_per_s"):
+            out["batch"]["speedup_vs_oracle_pool"] = round(
+                out["batch"]["circuits_per_s"] / cp["circuits_per_s"], 1)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -113,7 +113,11 @@ __device__ __forceinline__ void dense1_regs(C* a, const T* m, uint32_t rt,
 
 // The same update with the matrix chosen per pair by tile-local bit mbit:
 // m0 where the bit is 0, m1 where it is 1 (mbit differs from the target),
-// applied only where every bit of lctrl is 1.
+// applied only where every bit of lctrl is 1.  Each pair takes both uniform
+// matrices in turn and keeps the one its bits select: twice the FMAs of a
+// plain op, but the matrices stay in scalar registers (selecting one per
+// pair in vector registers set the register peak of the whole kernel, for
+// an op class that circuits rarely produce).
 template <int I, int R, typename C, typename T>
 __device__ __forceinline__ void dense1_mux_regs(C* a, const T* m0,
                                                 const T* m1, uint32_t rt,
@@ -124,14 +128,17 @@ __device__ __forceinline__ void dense1_mux_regs(C* a, const T* m0,
     if (j & (1 << I)) continue;
     const int j1 = j | (1 << I);
     const bool sel = (((rt >> mbit) | (lr[j] >> mbit)) & 1u) != 0;
-    T m[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) m[e] = sel ? m1[e] : m0[e];
-    C y0 = a[j], y1 = a[j1];
-    pair2x2<false>(y0, y1, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7]);
     const bool on = ((rt & lctrl) | (lr[j] & lctrl)) == lctrl;
-    a[j] = csel(on, y0, a[j]);
-    a[j1] = csel(on, y1, a[j1]);
+    C y0 = a[j], y1 = a[j1];
+    pair2x2<true>(y0, y1, m0[0], m0[1], m0[2], m0[3], m0[4], m0[5], m0[6],
+                  m0[7]);
+    a[j] = csel(on && !sel, y0, a[j]);
+    a[j1] = csel(on && !sel, y1, a[j1]);
+    C z0 = a[j], z1 = a[j1];
+    pair2x2<true>(z0, z1, m1[0], m1[1], m1[2], m1[3], m1[4], m1[5], m1[6],
+                  m1[7]);
+    a[j] = csel(on && sel, z0, a[j]);
+    a[j1] = csel(on && sel, z1, a[j1]);
   }
 }
 
