@@ -96,7 +96,9 @@ __device__ __forceinline__ void batch_phase_body(
           a[j].y = T(0);
         }
       }
-      tile_apply<T, RB>(a, lds, pass, segs, ops, base, tid, active);
+      // complex64 with 16 registers re-lays out in halves (half the LDS)
+      tile_apply<T, RB, sizeof(T) == 4 && RB == 4>(a, lds, pass, segs, ops,
+                                                  base, tid, active);
       if (active) {
         if (last) {
           const char* ob =
@@ -159,6 +161,14 @@ static const void* batch_fn() {
     return reinterpret_cast<const void*>(&batch_phase_kernel<T, OUT, RB>);
 }
 
+// LDS of one work-group: the tile, at 4 bytes per amplitude where the
+// re-layouts go in halves (complex64, 16 registers per thread).
+template <typename T, int RB>
+static size_t batch_lds_bytes(int L) {
+  using C = typename CxT<T>::type;
+  return (sizeof(T) == 4 && RB == 4) ? size_t(4) << L : size_t(sizeof(C)) << L;
+}
+
 template <typename T, typename OUT, int RB>
 static hipError_t batch_launch_t(const BatchCircuit* circs,
                                  const TilePass* passes, const TileSeg* segs,
@@ -177,7 +187,7 @@ static hipError_t batch_launch_t(const BatchCircuit* circs,
                                    160 * 1024);
   });
   if (attr_err != hipSuccess) return attr_err;
-  const size_t lds = size_t(sizeof(C)) << L;
+  const size_t lds = batch_lds_bytes<T, RB>(L);
   const size_t phases = hp.phase_tiles.size();
   for (size_t p = 0; p < phases; ++p) {
     const uint64_t tiles = hp.phase_tiles[p];
@@ -198,6 +208,7 @@ static hipError_t batch_launch_t(const BatchCircuit* circs,
 }
 
 // Resident work-groups per CU of the batch kernel for (prec, out, rb, L).
+// (Its LDS: batch_lds_bytes.)
 template <typename T, typename OUT, int RB>
 static int batch_occupancy_t(int L) {
   using C = typename CxT<T>::type;
@@ -206,7 +217,7 @@ static int batch_occupancy_t(int L) {
                             160 * 1024);
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &n, batch_fn<T, OUT, RB>(), 256, size_t(sizeof(C)) << L) !=
+          &n, batch_fn<T, OUT, RB>(), 256, batch_lds_bytes<T, RB>(L)) !=
       hipSuccess) {
     (void)hipGetLastError();
     return 0;

@@ -150,7 +150,9 @@ __device__ __forceinline__ void tile_body(typename CxT<T>::type* __restrict__ am
       a[j] = *reinterpret_cast<const C*>(wp + ro + lane_off);
     }
   }
-  tile_apply<T, RB>(a, lds, pass, segs, ops, base, tid, true);
+  // complex64 with 16 registers re-lays out in halves (half the LDS)
+  tile_apply<T, RB, sizeof(T) == 4 && RB == 4>(a, lds, pass, segs, ops, base,
+                                              tid, true);
   // The store addresses are formed again from the few values they derive
   // from (opaque to the compiler), so that the sixteen register addresses
   // are not held in scalar registers across the op loop.
@@ -213,11 +215,15 @@ static const void* tile_fn() {
 }
 
 template <typename T, int RB, int V>
-static hipError_t tile_launch(void* amp, int n, int L, const TilePass* pass,
-                              const TileSeg* segs, const TileOp* ops,
-                              hipStream_t stream) {
+static hipError_t tile_launch(void* amp, int n, int L, bool outputs,
+                              const TilePass* pass, const TileSeg* segs,
+                              const TileOp* ops, hipStream_t stream) {
   using C = typename CxT<T>::type;
-  const size_t lds = size_t(sizeof(C)) << L;
+  // complex64 with 16 registers re-lays out in halves (4 bytes per
+  // amplitude); the folded outputs stage FP64 values (8 bytes)
+  const size_t lds = (sizeof(T) == 4 && RB == 4 && !outputs)
+                         ? size_t(4) << L
+                         : size_t(sizeof(C)) << L;
   // set once per kernel function; callers on several threads (the server's
   // scheduler and its clients) reach this together, hence call_once
   static std::once_flag once;
@@ -248,7 +254,9 @@ hipError_t launch_tile(int prec, int rb, void* amp, int n,
   const bool boff32 = (host_pass.flags & kPassLane32) != 0;
   if (L - rb < 0 || L - rb > 9 || L > kMaxTileBits || n - L > 31)
     return hipErrorInvalidValue;
-#define QSV_T(T, RBV, V) return tile_launch<T, RBV, V>(amp, n, L, pass, segs, ops, stream)
+  const bool outputs = (host_pass.flags & kPassOutputs) != 0;
+#define QSV_T(T, RBV, V) \
+  return tile_launch<T, RBV, V>(amp, n, L, outputs, pass, segs, ops, stream)
   if (prec == 1) {
     if (rb == 3) {
       if (boff32) QSV_T(float, 3, 1);

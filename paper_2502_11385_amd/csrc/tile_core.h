@@ -363,6 +363,60 @@ __device__ __forceinline__ void relayout(C* a, C* lds, const Layout<RB>& from,
   lds_barrier();
 }
 
+// complex64 re-layout in two halves (the real parts, then the imaginary
+// parts), each through a 4-byte-per-amplitude copy of the tile: half the
+// LDS of relayout(), so that more work-groups fit on a CU, for two more
+// barriers and twice the LDS instructions.  The swizzle spreads 4-byte
+// elements over the 32 banks the way lds_swz spreads 8-byte ones.
+__device__ __forceinline__ uint32_t lds_swz4(uint32_t r) {
+  return r ^ (((r >> 5) ^ (r >> 10)) & 31u);
+}
+
+template <int RB, typename C>
+__device__ __forceinline__ void relayout_halves(C* a, C* lds,
+                                                const Layout<RB>& from,
+                                                const Layout<RB>& to,
+                                                uint32_t tid, bool active) {
+  constexpr int R = 1 << RB;
+  uint32_t sf[R], st[R];
+  {
+    uint32_t bf[RB], bt[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      bf[i] = __builtin_amdgcn_readfirstlane(lds_swz4(1u << from.rb[i]) * 4u);
+      bt[i] = __builtin_amdgcn_readfirstlane(lds_swz4(1u << to.rb[i]) * 4u);
+    }
+    sf[0] = st[0] = 0;
+#pragma unroll
+    for (int j = 1; j < R; ++j) {
+      sf[j] = sf[j & (j - 1)] ^ bf[__builtin_ctz(j)];
+      st[j] = st[j & (j - 1)] ^ bt[__builtin_ctz(j)];
+    }
+  }
+  const uint32_t lb = lds_address(lds);
+  const uint32_t rf = lb + lds_swz4(thread_local_base(from, tid)) * 4u;
+  const uint32_t rt = lb + lds_swz4(thread_local_base(to, tid)) * 4u;
+  typedef __attribute__((address_space(3))) float lds_float;
+  // threads beyond the tile (active == false) only join the barriers
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        *(lds_float*)(size_t(rf ^ sf[j])) = h ? a[j].y : a[j].x;
+    }
+    lds_barrier();
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const float v = *(const lds_float*)(size_t(rt ^ st[j]));
+        if (h) a[j].y = v; else a[j].x = v;
+      }
+    }
+    lds_barrier();
+  }
+}
+
 // e^{2 pi i t / 2^32} for a fixed-point fraction of a turn.  The top 24
 // bits go through sincospi exactly (an int32 with its low 8 bits clear is
 // exact in FP32); the low 8 bits, below 4e-7 rad, enter to first order.
@@ -534,7 +588,7 @@ __device__ __forceinline__ void pin_op_fields(OpFields<T>& f) {
 // in the I/O layout on entry and is left in the I/O layout on exit.  `base`
 // is the tile's global index with all tile bits zero (outer controls and
 // diagonal bits outside the tile are read from it).
-template <typename T, int RB>
+template <typename T, int RB, bool HALVES = false>
 __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
                                            typename CxT<T>::type* lds,
                                            const TilePass* pass,
@@ -556,7 +610,12 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
     Layout<RB> lay;
 #pragma unroll
     for (int i = 0; i < RB; ++i) lay.rb[i] = sp[s].reg_bits[i];
-    if (!same_layout(cur, lay)) relayout<T, RB>(a, lds, cur, lay, tid, active);
+    if (!same_layout(cur, lay)) {
+      if constexpr (HALVES && sizeof(T) == 4)
+        relayout_halves<RB>(a, lds, cur, lay, tid, active);
+      else
+        relayout<T, RB>(a, lds, cur, lay, tid, active);
+    }
     cur = lay;
     const uint32_t rt = thread_local_base(lay, tid);
     const int o_end = sp[s].op_end;
@@ -689,7 +748,12 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
       }
     }
   }
-  if (!same_layout(cur, io)) relayout<T, RB>(a, lds, cur, io, tid, active);
+  if (!same_layout(cur, io)) {
+    if constexpr (HALVES && sizeof(T) == 4)
+      relayout_halves<RB>(a, lds, cur, io, tid, active);
+    else
+      relayout<T, RB>(a, lds, cur, io, tid, active);
+  }
 }
 
 // Global offsets of a thread's registers in the I/O layout: register j of
