@@ -417,15 +417,38 @@ __device__ __forceinline__ void relayout_halves(C* a, C* lds,
   }
 }
 
-// e^{2 pi i t / 2^32} for a fixed-point fraction of a turn.  The top 24
-// bits go through sincospi exactly (an int32 with its low 8 bits clear is
-// exact in FP32); the low 8 bits, below 4e-7 rad, enter to first order.
+// e^{2 pi i t / 2^32} for a fixed-point fraction of a turn, from the
+// angle's octant and a Taylor polynomial on [0, pi/4].  The top three bits
+// of t give the octant o; the rest, f < 2^29, the angle inside it.  In odd
+// octants the polynomial takes the complementary angle pi/4 - x (from
+// 2^29 - f), so that its argument stays in [0, pi/4]; then cos and sin of
+// the whole angle are those of the octant's reflection:
+//   o:   0    1    2    3    4    5    6    7
+//   cos  c    s   -s   -c   -c   -s    s    c
+//   sin  s    c    c    s   -s   -c   -c   -s
+// Truncating sin after x^9 / 9! and cos after x^10 / 10! leaves below 2e-9
+// on [0, pi/4], under FP32 rounding.  Few registers: it runs while the
+// whole tile is live.
 __device__ __forceinline__ float2 turn_phase32(uint32_t t) {
-  const float y = float(int32_t(t & ~0xFFu)) * 0x1p-31f;
-  float sn, cs;
-  sincospif(y, &sn, &cs);
-  const float d = float(t & 0xFFu) * (3.14159265358979f * 0x1p-31f);
-  return make_float2(__builtin_fmaf(-sn, d, cs), __builtin_fmaf(cs, d, sn));
+  const uint32_t o = t >> 29;
+  const uint32_t f = t & 0x1FFFFFFFu;
+  const uint32_t g = (o & 1u) ? 0x20000000u - f : f;
+  const float x = float(g) * (6.28318530717958648f * 0x1p-32f);
+  const float x2 = x * x;
+  float s = __builtin_fmaf(x2, 1.0f / 362880.0f, -1.0f / 5040.0f);
+  s = __builtin_fmaf(x2, s, 1.0f / 120.0f);
+  s = __builtin_fmaf(x2, s, -1.0f / 6.0f);
+  s = __builtin_fmaf(x2 * x, s, x);
+  float c = __builtin_fmaf(x2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+  c = __builtin_fmaf(x2, c, -1.0f / 720.0f);
+  c = __builtin_fmaf(x2, c, 1.0f / 24.0f);
+  c = __builtin_fmaf(x2, c, -0.5f);
+  c = __builtin_fmaf(x2, c, 1.0f);
+  const bool swap = ((o + 1u) >> 1) & 1u;  // octants 1, 2, 5, 6
+  const float cv = swap ? s : c, sv = swap ? c : s;
+  const bool neg_c = ((o + 2u) >> 2) & 1u;  // octants 2..5
+  const bool neg_s = (o >> 2) & 1u;         // octants 4..7
+  return make_float2(neg_c ? -cv : cv, neg_s ? -sv : sv);
 }
 
 // e^{2 pi i t / 2^64} in FP64 (the int64 -> double rounding is 2^-53 of a
