@@ -15,12 +15,18 @@
 // This is the single-GPU form of the paper's chunking with cache blocking
 // (Section III.B): a tile is a 2^L-amplitude chunk, and a pass runs every
 // gate that the planner could move onto the chunk's qubits.
+#include <algorithm>
 #include <mutex>
 
 #include "reduce_core.h"
 #include "tile_core.h"
 
 namespace qsv {
+
+// Tile kernels whose re-layouts go in halves (one component per amplitude
+// through LDS): complex64 with 16 registers per thread, and complex128.
+template <typename T, int RB>
+constexpr bool kHalves = (sizeof(T) == 4 && RB == 4) || sizeof(T) == 8;
 
 // Tile index -> global index of the tile's first amplitude: the index's
 // bits spread over the non-tile qubits.
@@ -150,9 +156,9 @@ __device__ __forceinline__ void tile_body(typename CxT<T>::type* __restrict__ am
       a[j] = *reinterpret_cast<const C*>(wp + ro + lane_off);
     }
   }
-  // complex64 with 16 registers re-lays out in halves (half the LDS)
-  tile_apply<T, RB, sizeof(T) == 4 && RB == 4>(a, lds, pass, segs, ops, base,
-                                              tid, true);
+  // complex64 with 16 registers and complex128 re-lay out in halves (half
+  // the LDS)
+  tile_apply<T, RB, kHalves<T, RB>>(a, lds, pass, segs, ops, base, tid, true);
   // The store addresses are formed again from the few values they derive
   // from (opaque to the compiler), so that the sixteen register addresses
   // are not held in scalar registers across the op loop.
@@ -219,11 +225,11 @@ static hipError_t tile_launch(void* amp, int n, int L, bool outputs,
                               const TilePass* pass, const TileSeg* segs,
                               const TileOp* ops, hipStream_t stream) {
   using C = typename CxT<T>::type;
-  // complex64 with 16 registers re-lays out in halves (4 bytes per
-  // amplitude); the folded outputs stage FP64 values (8 bytes)
-  const size_t lds = (sizeof(T) == 4 && RB == 4 && !outputs)
-                         ? size_t(4) << L
-                         : size_t(sizeof(C)) << L;
+  // re-layouts in halves need one component per amplitude; the folded
+  // outputs stage FP64 values (8 bytes)
+  const size_t lds = !kHalves<T, RB> ? size_t(sizeof(C)) << L
+                     : outputs      ? std::max(size_t(8), sizeof(T)) << L
+                                    : size_t(sizeof(T)) << L;
   // set once per kernel function; callers on several threads (the server's
   // scheduler and its clients) reach this together, hence call_once
   static std::once_flag once;

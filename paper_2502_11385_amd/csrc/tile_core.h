@@ -363,28 +363,38 @@ __device__ __forceinline__ void relayout(C* a, C* lds, const Layout<RB>& from,
   lds_barrier();
 }
 
-// complex64 re-layout in two halves (the real parts, then the imaginary
-// parts), each through a 4-byte-per-amplitude copy of the tile: half the
+// Re-layout in two halves (the real parts, then the imaginary parts), each
+// through a copy of the tile with one component per amplitude: half the
 // LDS of relayout(), so that more work-groups fit on a CU, for two more
-// barriers and twice the LDS instructions.  The swizzle spreads 4-byte
-// elements over the 32 banks the way lds_swz spreads 8-byte ones.
+// barriers and twice the LDS instructions.  4-byte components (complex64)
+// take a swizzle over the 32 banks like lds_swz's; 8-byte components
+// (complex128) take lds_swz's own 8-byte swizzle.
 __device__ __forceinline__ uint32_t lds_swz4(uint32_t r) {
   return r ^ (((r >> 5) ^ (r >> 10)) & 31u);
 }
 
-template <int RB, typename C>
+template <typename T>
+__device__ __forceinline__ uint32_t half_swz(uint32_t r) {
+  if constexpr (sizeof(T) == 4)
+    return lds_swz4(r);
+  else
+    return lds_swz<float>(r);
+}
+
+template <typename T, int RB, typename C>
 __device__ __forceinline__ void relayout_halves(C* a, C* lds,
                                                 const Layout<RB>& from,
                                                 const Layout<RB>& to,
                                                 uint32_t tid, bool active) {
   constexpr int R = 1 << RB;
+  constexpr uint32_t E = sizeof(T);
   uint32_t sf[R], st[R];
   {
     uint32_t bf[RB], bt[RB];
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
-      bf[i] = __builtin_amdgcn_readfirstlane(lds_swz4(1u << from.rb[i]) * 4u);
-      bt[i] = __builtin_amdgcn_readfirstlane(lds_swz4(1u << to.rb[i]) * 4u);
+      bf[i] = __builtin_amdgcn_readfirstlane(half_swz<T>(1u << from.rb[i]) * E);
+      bt[i] = __builtin_amdgcn_readfirstlane(half_swz<T>(1u << to.rb[i]) * E);
     }
     sf[0] = st[0] = 0;
 #pragma unroll
@@ -394,22 +404,22 @@ __device__ __forceinline__ void relayout_halves(C* a, C* lds,
     }
   }
   const uint32_t lb = lds_address(lds);
-  const uint32_t rf = lb + lds_swz4(thread_local_base(from, tid)) * 4u;
-  const uint32_t rt = lb + lds_swz4(thread_local_base(to, tid)) * 4u;
-  typedef __attribute__((address_space(3))) float lds_float;
+  const uint32_t rf = lb + half_swz<T>(thread_local_base(from, tid)) * E;
+  const uint32_t rt = lb + half_swz<T>(thread_local_base(to, tid)) * E;
+  typedef __attribute__((address_space(3))) T lds_t;
   // threads beyond the tile (active == false) only join the barriers
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     if (active) {
 #pragma unroll
       for (int j = 0; j < R; ++j)
-        *(lds_float*)(size_t(rf ^ sf[j])) = h ? a[j].y : a[j].x;
+        *(lds_t*)(size_t(rf ^ sf[j])) = h ? a[j].y : a[j].x;
     }
     lds_barrier();
     if (active) {
 #pragma unroll
       for (int j = 0; j < R; ++j) {
-        const float v = *(const lds_float*)(size_t(rt ^ st[j]));
+        const T v = *(const lds_t*)(size_t(rt ^ st[j]));
         if (h) a[j].y = v; else a[j].x = v;
       }
     }
@@ -634,8 +644,8 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
 #pragma unroll
     for (int i = 0; i < RB; ++i) lay.rb[i] = sp[s].reg_bits[i];
     if (!same_layout(cur, lay)) {
-      if constexpr (HALVES && sizeof(T) == 4)
-        relayout_halves<RB>(a, lds, cur, lay, tid, active);
+      if constexpr (HALVES)
+        relayout_halves<T, RB>(a, lds, cur, lay, tid, active);
       else
         relayout<T, RB>(a, lds, cur, lay, tid, active);
     }
@@ -772,8 +782,8 @@ __device__ __forceinline__ void tile_apply(typename CxT<T>::type* a,
     }
   }
   if (!same_layout(cur, io)) {
-    if constexpr (HALVES && sizeof(T) == 4)
-      relayout_halves<RB>(a, lds, cur, io, tid, active);
+    if constexpr (HALVES)
+      relayout_halves<T, RB>(a, lds, cur, io, tid, active);
     else
       relayout<T, RB>(a, lds, cur, io, tid, active);
   }
