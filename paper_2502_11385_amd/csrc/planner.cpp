@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstring>
 #include <array>
+#include <functional>
 #include <map>
 #include <tuple>
 
@@ -373,6 +374,268 @@ static bool is_identity2(const double* m) {
   return true;
 }
 
+// Which op absorbs a two-qubit diagonal gate (a CZ, say) decides how many
+// one-target gates merge: the gates on qubit a before and after a CZ(a, b)
+// fuse into one op muxed by b, but only one of a and b can take the CZ (the
+// other's op then reads a or b in the middle of its run).  The emitter
+// below gives a pending diagonal gate to the first dense gate processed
+// that touches it, so the processing order inside a segment is the lever.
+//
+// Model, per pass and per qubit q: the dense one-target gates on q in
+// order; a diagonal gate on q and one other qubit b is "owned" by the side
+// whose next gate absorbs it (forced when only one side has a later gate in
+// the pass, or when the two next gates lie in different register segments:
+// the earlier segment's takes it), and is then a read of b attached to q's
+// next gate.  A diagonal
+// gate owned by the other side, or a dense gate with q as a control,
+// between two gates on q keeps them apart.  Gates on q join into one op
+// when nothing keeps them apart and the reads attached to them are all of
+// one qubit b, with no dense gate on b between the reads.  The most joins
+// on a qubit under a given ownership is a small dynamic program over its
+// gates; the ownership of each shared diagonal gate is improved by local
+// search (flip while the two qubits' joins grow) from two starts, the
+// lower qubit owning every shared gate and the higher one.  Each segment is
+// then put in a commuting order (a topological order of its gates, earliest
+// first) where the owner's next gate comes before the other qubit's.  The
+// emitter still checks every merge itself: the order changes op counts,
+// never results.
+static std::vector<std::vector<int>> merge_order(
+    const Pass& p, const std::vector<HostGate>& G) {
+  std::vector<int> order, seg_of;
+  std::vector<std::vector<int>> out(p.segs.size());
+  for (size_t si = 0; si < p.segs.size(); ++si) {
+    out[si] = p.segs[si].gates;
+    for (int gi : p.segs[si].gates) {
+      order.push_back(gi);
+      seg_of.push_back(int(si));
+    }
+  }
+  const int N = int(order.size());
+  std::vector<int> target(N);
+  // per qubit (compressed rows): the positions of the gates touching it,
+  // and of the dense gates on it as target
+  std::array<int, 65> eo, to;
+  eo.fill(0);
+  to.fill(0);
+  for (int i = 0; i < N; ++i) {
+    const HostGate& g = G[order[i]];
+    target[i] = (!g.diagonal && g.k == 1) ? g.t[0] : -1;
+    for (uint64_t m = g.touch(); m; m &= m - 1) ++eo[__builtin_ctzll(m) + 1];
+    if (target[i] >= 0) ++to[target[i] + 1];
+  }
+  for (int q = 0; q < 64; ++q) {
+    eo[q + 1] += eo[q];
+    to[q + 1] += to[q];
+  }
+  std::vector<int> ev(eo[64]), tp(to[64]);
+  {
+    std::array<int, 64> fe, ft;
+    std::copy(eo.begin(), eo.begin() + 64, fe.begin());
+    std::copy(to.begin(), to.begin() + 64, ft.begin());
+    for (int i = 0; i < N; ++i) {
+      for (uint64_t m = G[order[i]].touch(); m; m &= m - 1)
+        ev[fe[__builtin_ctzll(m)]++] = i;
+      if (target[i] >= 0) tp[ft[target[i]]++] = i;
+    }
+  }
+  // dense gates on target b before position i
+  auto version = [&](int b, int i) {
+    return int(std::lower_bound(tp.begin() + to[b], tp.begin() + to[b + 1], i) -
+               (tp.begin() + to[b]));
+  };
+  // next position after i with a dense gate on target q (-1: none)
+  auto next_on = [&](int q, int i) {
+    auto it = std::upper_bound(tp.begin() + to[q], tp.begin() + to[q + 1], i);
+    return it == tp.begin() + to[q + 1] ? -1 : *it;
+  };
+  // two-qubit diagonal gates either side could absorb; forced owners
+  std::vector<int> owner(N, -1), shared;
+  for (int d = 0; d < N; ++d) {
+    const HostGate& g = G[order[d]];
+    if (!g.diagonal) continue;
+    const uint64_t tm = g.touch();
+    if (popc(tm) == 1) {
+      owner[d] = __builtin_ctzll(tm);
+    } else if (popc(tm) == 2) {
+      const int a = __builtin_ctzll(tm), b = 63 - __builtin_clzll(tm);
+      // the earlier segment's gate absorbs it; in one segment, either
+      const int na = next_on(a, d), nb = next_on(b, d);
+      if (na >= 0 && nb >= 0 && seg_of[na] == seg_of[nb]) shared.push_back(d);
+      else if (na >= 0 && (nb < 0 || seg_of[na] < seg_of[nb])) owner[d] = a;
+      else if (nb >= 0) owner[d] = b;
+    }
+  }
+  if (shared.empty()) return out;
+  // the most joins on qubit q under `owner`
+  auto joins = [&](int q) -> int {
+    int bn = -1, bm = -1, mq = -1, mv = -1;  // best per op state
+    bool first = true, apart = false, prev_plain = false;
+    int rq = -1, rv = -1;
+    bool rbad = false;
+    auto read = [&](int b, int v) {
+      if (rq < 0) {
+        rq = b;
+        rv = v;
+      } else if (rq != b || rv != v) {
+        rbad = true;
+      }
+    };
+    for (int e = eo[q]; e < eo[q + 1]; ++e) {
+      const int i = ev[e];
+      const HostGate& g = G[order[i]];
+      if (target[i] != q) {
+        if (!g.diagonal || owner[i] != q || popc(g.touch()) > 2) {
+          apart = true;  // q is read by another op, or the gate stands apart
+        } else if (popc(g.touch()) == 2) {
+          const int b = __builtin_ctzll(g.touch() & ~(uint64_t(1) << q));
+          read(b, version(b, i));
+        }
+        continue;
+      }
+      const bool plain = g.c > 1;
+      if (g.c == 1) read(g.ctl[0], version(g.ctl[0], i));
+      if (rbad || plain) {  // the reads are emitted apart from the gate
+        apart = true;
+        rq = rv = -1;
+        if (g.c == 1) {
+          rq = g.ctl[0];
+          rv = version(rq, i);
+        }
+      }
+      const bool join = !first && !apart && !plain && !prev_plain;
+      const int top = std::max(bn, bm);
+      if (first) {
+        bn = rq < 0 ? 0 : -1;
+        bm = rq < 0 ? -1 : 0;
+        mq = rq;
+        mv = rv;
+      } else if (rq < 0) {
+        const int nn = std::max(top, join && bn >= 0 ? bn + 1 : -1);
+        bm = join && bm >= 0 ? bm + 1 : -1;
+        bn = nn;
+      } else {
+        int nm = top;
+        if (join && bn >= 0) nm = std::max(nm, bn + 1);
+        if (join && bm >= 0 && mq == rq && mv == rv) nm = std::max(nm, bm + 1);
+        bm = nm;
+        bn = -1;
+        mq = rq;
+        mv = rv;
+      }
+      if (plain) {  // a controlled op stands alone
+        bn = std::max(bn, bm);
+        bm = -1;
+      }
+      first = false;
+      apart = false;
+      prev_plain = plain;
+      rq = rv = -1;
+      rbad = false;
+    }
+    return std::max(0, std::max(bn, bm));
+  };
+  auto other = [&](int d, int q) {
+    return __builtin_ctzll(G[order[d]].touch() & ~(uint64_t(1) << q));
+  };
+  std::vector<int> best_owner;
+  int best_total = -1;
+  for (int start = 0; start < 2; ++start) {
+    for (int d : shared) {
+      const uint64_t tm = G[order[d]].touch();
+      owner[d] = start == 0 ? __builtin_ctzll(tm) : 63 - __builtin_clzll(tm);
+    }
+    std::array<int, 64> jq;
+    jq.fill(0);
+    int total = 0;
+    for (int q = 0; q < 64; ++q)
+      if (eo[q + 1] > eo[q]) total += (jq[q] = joins(q));
+    for (int round = 0; round < 8; ++round) {
+      bool better = false;
+      for (int d : shared) {
+        const int a = owner[d], b = other(d, a);
+        owner[d] = b;
+        const int ja = joins(a), jb = joins(b);
+        if (ja + jb > jq[a] + jq[b]) {
+          total += ja + jb - jq[a] - jq[b];
+          jq[a] = ja;
+          jq[b] = jb;
+          better = true;
+        } else {
+          owner[d] = a;
+        }
+      }
+      if (!better) break;
+    }
+    if (total > best_total) {
+      best_total = total;
+      best_owner = owner;
+    }
+  }
+  owner.swap(best_owner);
+  // per segment: dependency edges (gates that do not commute keep their
+  // order: per qubit, a dense gate after everything since the previous
+  // dense gate, anything else after the previous dense gate) plus "owner's
+  // next gate first" edges; Kahn's algorithm taking the earliest ready
+  // gate; a cycle keeps the segment's order
+  std::vector<std::vector<int>> first_of(N);
+  for (int d : shared) {
+    const int ua = next_on(owner[d], d), ub = next_on(other(d, owner[d]), d);
+    if (ua > ub && seg_of[ua] == seg_of[ub]) first_of[ua].push_back(ub);
+  }
+  int lo = 0;
+  for (size_t si = 0; si < p.segs.size(); ++si) {
+    const int m = int(p.segs[si].gates.size()), hi = lo + m;
+    bool any = false;
+    for (int i = lo; i < hi && !any; ++i) any = !first_of[i].empty();
+    if (any) {
+      std::vector<std::vector<int>> succ(m);
+      std::vector<int> indeg(m, 0);
+      auto edge = [&](int i, int j) {
+        succ[i].push_back(j);
+        ++indeg[j];
+      };
+      std::array<int, 64> last_dense;
+      last_dense.fill(-1);
+      std::array<std::vector<int>, 64> since;
+      for (int j = 0; j < m; ++j) {
+        const HostGate& g = G[order[lo + j]];
+        for (uint64_t t = g.touch(); t; t &= t - 1) {
+          const int q = __builtin_ctzll(t);
+          if (last_dense[q] >= 0) edge(last_dense[q], j);
+          if (g.dense() >> q & 1) {
+            for (int i : since[q]) edge(i, j);
+            since[q].clear();
+            last_dense[q] = j;
+          } else {
+            since[q].push_back(j);
+          }
+        }
+      }
+      for (int i = lo; i < hi; ++i)
+        for (int j : first_of[i]) edge(i - lo, j - lo);
+      std::vector<int> res;
+      std::vector<int> heap;  // min-heap of ready local indices
+      for (int i = 0; i < m; ++i)
+        if (indeg[i] == 0) heap.push_back(i);
+      std::make_heap(heap.begin(), heap.end(), std::greater<int>());
+      while (!heap.empty()) {
+        std::pop_heap(heap.begin(), heap.end(), std::greater<int>());
+        const int i = heap.back();
+        heap.pop_back();
+        res.push_back(order[lo + i]);
+        for (int j : succ[i])
+          if (--indeg[j] == 0) {
+            heap.push_back(j);
+            std::push_heap(heap.begin(), heap.end(), std::greater<int>());
+          }
+      }
+      if (int(res.size()) == m) out[si] = std::move(res);
+    }
+    lo = hi;
+  }
+  return out;
+}
+
 std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
                            int RB, std::vector<TilePass>* tpasses,
                            std::vector<TileSeg>* tsegs,
@@ -722,6 +985,7 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
     return m;
   };
   std::vector<int> pend;
+  const std::vector<std::vector<int>> seg_order = merge_order(p, G);
   for (size_t si = 0; si < p.segs.size(); ++si) {
     const auto& sg = p.segs[si];
     TileSeg ts = {};
@@ -735,7 +999,7 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
       const int q = p.q[sg.reg_bits[i]];
       if (has_pp[q]) pp_seg[q] = int(si);
     }
-    for (int gi : sg.gates) {
+    for (int gi : seg_order[si]) {
       const HostGate& g = G[gi];
       if (g.diagonal) {
         pend.push_back(gi);
