@@ -159,10 +159,40 @@ static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
       pending.erase(pending.begin());
       continue;
     }
-    uint64_t Q = (m >= 64) ? ~0ull : ((1ull << m) - 1);
-    std::vector<int> taken;
-    greedy(G, &pending, &Q, L,
-           [](const HostGate& g) { return g.dense(); }, tileable, &taken);
+    // The tile's qubit set: the low qubits plus either the first qubits the
+    // gates in order ask for (greedy) or a window of L - m consecutive
+    // qubits, whichever takes the most dense gates.  A pass costs about as
+    // much as several dense ops whatever it holds (one HBM round trip, the
+    // re-layouts, the tile's load and store), so fewer, fuller passes win;
+    // windows follow the light cone of nearest-neighbour circuits, where the
+    // greedy choice takes one or two layers of a window's gates per pass.
+    const uint64_t low = (m >= 64) ? ~0ull : ((1ull << m) - 1);
+    auto dense_count = [&](const std::vector<int>& t) {
+      int c = 0;
+      for (int gi : t) c += !G[gi].diagonal;
+      return c;
+    };
+    uint64_t Q = low;
+    std::vector<int> taken, rest = pending;
+    greedy(G, &rest, &Q, L, [](const HostGate& g) { return g.dense(); },
+           tileable, &taken);
+    int best = dense_count(taken);
+    for (int s0 = m; s0 + (L - m) <= n && L > m; ++s0) {
+      uint64_t W = low;
+      for (int q = s0; q < s0 + L - m; ++q) W |= uint64_t(1) << q;
+      std::vector<int> t2, r2 = pending;
+      uint64_t W2 = W;
+      greedy(G, &r2, &W2, L, [](const HostGate& g) { return g.dense(); },
+             tileable, &t2);
+      const int c = dense_count(t2);
+      if (c > best) {
+        best = c;
+        Q = W2;
+        taken.swap(t2);
+        rest.swap(r2);
+      }
+    }
+    pending.swap(rest);
     // Fill the tile's qubit set up to exactly L qubits (lowest free first).
     for (int q = 0; q < n && popc(Q) < L; ++q) Q |= 1ull << q;
 
