@@ -98,20 +98,21 @@ uint64_t plain_gate_bytes(const HostGate& g, int n, int b) {
 }
 
 // One greedy scan over `pending` in list order.  A gate is taken when it
-// commutes with every gate skipped before it in this scan and the bits it
-// requires fit into `set` (at most `capacity` bits).  Taken gates keep their
-// relative order; skipped gates stay pending in their order.
-template <class Need, class Ok>
+// commutes with every gate skipped before it in this scan, `ok` accepts its
+// index and the bits it requires fit into `set` (at most `capacity` bits).
+// Taken gates keep their relative order; skipped gates stay pending in
+// their order.  `took` hears of each gate taken, as it is taken.
+template <class Need, class Ok, class Took>
 static void greedy(const std::vector<HostGate>& G, std::vector<int>* pending,
                    uint64_t* set, int capacity, Need need, Ok ok,
-                   std::vector<int>* taken) {
+                   std::vector<int>* taken, Took took) {
   std::vector<int> rest;
   uint64_t blk_touch = 0, blk_dense = 0;
   for (int gi : *pending) {
     const HostGate& g = G[gi];
     bool take = false;
     bool conflict = (g.dense() & blk_touch) || (g.touch() & blk_dense);
-    if (!conflict && ok(g)) {
+    if (!conflict && ok(gi)) {
       uint64_t want = need(g) & ~*set;
       if (popc(*set | want) <= capacity) {
         *set |= want;
@@ -120,6 +121,7 @@ static void greedy(const std::vector<HostGate>& G, std::vector<int>* pending,
     }
     if (take) {
       taken->push_back(gi);
+      took(gi);
     } else {
       rest.push_back(gi);
       blk_touch |= g.touch();
@@ -131,6 +133,299 @@ static void greedy(const std::vector<HostGate>& G, std::vector<int>* pending,
 
 static bool tileable(const HostGate& g) {
   return g.diagonal ? (g.masked_phase || g.k <= 2) : g.k == 1;
+}
+
+// Which op absorbs a two-qubit diagonal gate (a CZ, say) decides how many
+// one-target gates merge: the gates on qubit a before and after a CZ(a, b)
+// fuse into one op muxed by b, but only one of a and b can take the CZ (the
+// other's op then reads a or b in the middle of its run).  The emitter
+// below gives a pending diagonal gate to the first dense gate processed
+// that touches it, so the processing order inside a segment is the lever.
+//
+// Model, per pass and per qubit q: the dense one-target gates on q in
+// order; a diagonal gate on q and one other qubit b is "owned" by the side
+// whose next gate absorbs it (forced when only one side has a later gate in
+// the pass, or when the two next gates lie in different register segments:
+// the earlier segment's takes it), and is then a read of b attached to q's
+// next gate.  A diagonal
+// gate owned by the other side, or a dense gate with q as a control,
+// between two gates on q keeps them apart.  Gates on q join into one op
+// when nothing keeps them apart and the reads attached to them are all of
+// one qubit b, with no dense gate on b between the reads.  The most joins
+// on a qubit under a given ownership is a small dynamic program over its
+// gates; the ownership of each shared diagonal gate is improved by local
+// search (flip while the two qubits' joins grow) from two starts, the
+// lower qubit owning every shared gate and the higher one.  Each segment is
+// then put in a commuting order (a topological order of its gates, earliest
+// first) where the owner's next gate comes before the other qubit's.  The
+// emitter still checks every merge itself: the order changes op counts,
+// never results.  The segments themselves are built knowing the ownership
+// the pass would have with no segment boundaries, so that an owner's next
+// gate does not land in a later segment than the other side's (see
+// plan_tiled).
+// A pass's gates in processing order, with per-qubit rows (compressed) of
+// the positions touching each qubit and of the dense gates on it.
+struct PassOrder {
+  const std::vector<HostGate>& G;
+  std::vector<int> order, target, ev, tp;
+  std::array<int, 65> eo, to;
+  PassOrder(const std::vector<HostGate>& g, std::vector<int> ord)
+      : G(g), order(std::move(ord)) {
+    const int N = int(order.size());
+    target.resize(N);
+    eo.fill(0);
+    to.fill(0);
+    for (int i = 0; i < N; ++i) {
+      const HostGate& h = G[order[i]];
+      target[i] = (!h.diagonal && h.k == 1) ? h.t[0] : -1;
+      for (uint64_t m = h.touch(); m; m &= m - 1) ++eo[__builtin_ctzll(m) + 1];
+      if (target[i] >= 0) ++to[target[i] + 1];
+    }
+    for (int q = 0; q < 64; ++q) {
+      eo[q + 1] += eo[q];
+      to[q + 1] += to[q];
+    }
+    ev.resize(eo[64]);
+    tp.resize(to[64]);
+    std::array<int, 64> fe, ft;
+    std::copy(eo.begin(), eo.begin() + 64, fe.begin());
+    std::copy(to.begin(), to.begin() + 64, ft.begin());
+    for (int i = 0; i < N; ++i) {
+      for (uint64_t m = G[order[i]].touch(); m; m &= m - 1)
+        ev[fe[__builtin_ctzll(m)]++] = i;
+      if (target[i] >= 0) tp[ft[target[i]]++] = i;
+    }
+  }
+  int size() const { return int(order.size()); }
+  // dense gates on target b before position i
+  int version(int b, int i) const {
+    return int(std::lower_bound(tp.begin() + to[b], tp.begin() + to[b + 1], i) -
+               (tp.begin() + to[b]));
+  }
+  // next position after i with a dense gate on target q (-1: none)
+  int next_on(int q, int i) const {
+    auto it = std::upper_bound(tp.begin() + to[q], tp.begin() + to[q + 1], i);
+    return it == tp.begin() + to[q + 1] ? -1 : *it;
+  }
+  // the other qubit of the two-qubit gate at position d
+  int other(int d, int q) const {
+    return __builtin_ctzll(G[order[d]].touch() & ~(uint64_t(1) << q));
+  }
+};
+
+// The owner qubit of each diagonal gate of `po` (-1: none), by the model
+// above; `shared` receives the positions of the gates either side could
+// take.  With `seg_of`, a gate whose two next gates lie in different
+// segments goes to the earlier segment's side.
+static std::vector<int> choose_owners(const PassOrder& po,
+                                      const std::vector<int>* seg_of,
+                                      std::vector<int>* shared) {
+  const std::vector<HostGate>& G = po.G;
+  const int N = po.size();
+  std::vector<int> owner(N, -1);
+  shared->clear();
+  for (int d = 0; d < N; ++d) {
+    const HostGate& g = G[po.order[d]];
+    if (!g.diagonal) continue;
+    const uint64_t tm = g.touch();
+    if (popc(tm) == 1) {
+      owner[d] = __builtin_ctzll(tm);
+    } else if (popc(tm) == 2) {
+      const int a = __builtin_ctzll(tm), b = 63 - __builtin_clzll(tm);
+      const int na = po.next_on(a, d), nb = po.next_on(b, d);
+      const bool apart = seg_of && na >= 0 && nb >= 0 &&
+                         (*seg_of)[na] != (*seg_of)[nb];
+      if (na >= 0 && nb >= 0 && !apart) shared->push_back(d);
+      else if (na >= 0 && (nb < 0 || (*seg_of)[na] < (*seg_of)[nb])) owner[d] = a;
+      else if (nb >= 0) owner[d] = b;
+    }
+  }
+  if (shared->empty()) return owner;
+  // the most joins on qubit q under `owner`
+  auto joins = [&](int q) -> int {
+    int bn = -1, bm = -1, mq = -1, mv = -1;  // best per op state
+    bool first = true, apart = false, prev_plain = false;
+    int rq = -1, rv = -1;
+    bool rbad = false;
+    auto read = [&](int b, int v) {
+      if (rq < 0) {
+        rq = b;
+        rv = v;
+      } else if (rq != b || rv != v) {
+        rbad = true;
+      }
+    };
+    for (int e = po.eo[q]; e < po.eo[q + 1]; ++e) {
+      const int i = po.ev[e];
+      const HostGate& g = G[po.order[i]];
+      if (po.target[i] != q) {
+        if (!g.diagonal || owner[i] != q || popc(g.touch()) > 2) {
+          apart = true;  // q is read by another op, or the gate stands apart
+        } else if (popc(g.touch()) == 2) {
+          const int b = po.other(i, q);
+          read(b, po.version(b, i));
+        }
+        continue;
+      }
+      const bool plain = g.c > 1;
+      if (g.c == 1) read(g.ctl[0], po.version(g.ctl[0], i));
+      if (rbad || plain) {  // the reads are emitted apart from the gate
+        apart = true;
+        rq = rv = -1;
+        if (g.c == 1) {
+          rq = g.ctl[0];
+          rv = po.version(rq, i);
+        }
+      }
+      const bool join = !first && !apart && !plain && !prev_plain;
+      const int top = std::max(bn, bm);
+      if (first) {
+        bn = rq < 0 ? 0 : -1;
+        bm = rq < 0 ? -1 : 0;
+        mq = rq;
+        mv = rv;
+      } else if (rq < 0) {
+        const int nn = std::max(top, join && bn >= 0 ? bn + 1 : -1);
+        bm = join && bm >= 0 ? bm + 1 : -1;
+        bn = nn;
+      } else {
+        int nm = top;
+        if (join && bn >= 0) nm = std::max(nm, bn + 1);
+        if (join && bm >= 0 && mq == rq && mv == rv) nm = std::max(nm, bm + 1);
+        bm = nm;
+        bn = -1;
+        mq = rq;
+        mv = rv;
+      }
+      if (plain) {  // a controlled op stands alone
+        bn = std::max(bn, bm);
+        bm = -1;
+      }
+      first = false;
+      apart = false;
+      prev_plain = plain;
+      rq = rv = -1;
+      rbad = false;
+    }
+    return std::max(0, std::max(bn, bm));
+  };
+  std::vector<int> best_owner;
+  int best_total = -1;
+  for (int start = 0; start < 2; ++start) {
+    for (int d : *shared) {
+      const uint64_t tm = G[po.order[d]].touch();
+      owner[d] = start == 0 ? __builtin_ctzll(tm) : 63 - __builtin_clzll(tm);
+    }
+    std::array<int, 64> jq;
+    jq.fill(0);
+    int total = 0;
+    for (int q = 0; q < 64; ++q)
+      if (po.eo[q + 1] > po.eo[q]) total += (jq[q] = joins(q));
+    for (int round = 0; round < 8; ++round) {
+      bool better = false;
+      for (int d : *shared) {
+        const int a = owner[d], b = po.other(d, a);
+        owner[d] = b;
+        const int ja = joins(a), jb = joins(b);
+        if (ja + jb > jq[a] + jq[b]) {
+          total += ja + jb - jq[a] - jq[b];
+          jq[a] = ja;
+          jq[b] = jb;
+          better = true;
+        } else {
+          owner[d] = a;
+        }
+      }
+      if (!better) break;
+    }
+    if (total > best_total) {
+      best_total = total;
+      best_owner = owner;
+    }
+  }
+  return best_owner;
+}
+
+// The processing order of each segment of a tile pass (see above).
+static std::vector<std::vector<int>> merge_order(
+    const Pass& p, const std::vector<HostGate>& G) {
+  std::vector<int> order, seg_of;
+  std::vector<std::vector<int>> out(p.segs.size());
+  for (size_t si = 0; si < p.segs.size(); ++si) {
+    out[si] = p.segs[si].gates;
+    for (int gi : p.segs[si].gates) {
+      order.push_back(gi);
+      seg_of.push_back(int(si));
+    }
+  }
+  const PassOrder po(G, std::move(order));
+  std::vector<int> shared;
+  const std::vector<int> owner = choose_owners(po, &seg_of, &shared);
+  if (shared.empty()) return out;
+  // per segment: dependency edges (gates that do not commute keep their
+  // order: per qubit, a dense gate after everything since the previous
+  // dense gate, anything else after the previous dense gate) plus "owner's
+  // next gate first" edges; Kahn's algorithm taking the earliest ready
+  // gate; a cycle keeps the segment's order
+  const int N = po.size();
+  std::vector<std::vector<int>> first_of(N);
+  for (int d : shared) {
+    const int ua = po.next_on(owner[d], d),
+              ub = po.next_on(po.other(d, owner[d]), d);
+    if (ua > ub && seg_of[ua] == seg_of[ub]) first_of[ua].push_back(ub);
+  }
+  int lo = 0;
+  for (size_t si = 0; si < p.segs.size(); ++si) {
+    const int m = int(p.segs[si].gates.size()), hi = lo + m;
+    bool any = false;
+    for (int i = lo; i < hi && !any; ++i) any = !first_of[i].empty();
+    if (any) {
+      std::vector<std::vector<int>> succ(m);
+      std::vector<int> indeg(m, 0);
+      auto edge = [&](int i, int j) {
+        succ[i].push_back(j);
+        ++indeg[j];
+      };
+      std::array<int, 64> last_dense;
+      last_dense.fill(-1);
+      std::array<std::vector<int>, 64> since;
+      for (int j = 0; j < m; ++j) {
+        const HostGate& g = G[po.order[lo + j]];
+        for (uint64_t t = g.touch(); t; t &= t - 1) {
+          const int q = __builtin_ctzll(t);
+          if (last_dense[q] >= 0) edge(last_dense[q], j);
+          if (g.dense() >> q & 1) {
+            for (int i : since[q]) edge(i, j);
+            since[q].clear();
+            last_dense[q] = j;
+          } else {
+            since[q].push_back(j);
+          }
+        }
+      }
+      for (int i = lo; i < hi; ++i)
+        for (int j : first_of[i]) edge(i - lo, j - lo);
+      std::vector<int> res;
+      std::vector<int> heap;  // min-heap of ready local indices
+      for (int i = 0; i < m; ++i)
+        if (indeg[i] == 0) heap.push_back(i);
+      std::make_heap(heap.begin(), heap.end(), std::greater<int>());
+      while (!heap.empty()) {
+        std::pop_heap(heap.begin(), heap.end(), std::greater<int>());
+        const int i = heap.back();
+        heap.pop_back();
+        res.push_back(po.order[lo + i]);
+        for (int j : succ[i])
+          if (--indeg[j] == 0) {
+            heap.push_back(j);
+            std::push_heap(heap.begin(), heap.end(), std::greater<int>());
+          }
+      }
+      if (int(res.size()) == m) out[si] = std::move(res);
+    }
+    lo = hi;
+  }
+  return out;
 }
 
 static void add_plain(const std::vector<HostGate>& G, int gi, int n, int b,
@@ -167,6 +462,8 @@ static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
     // windows follow the light cone of nearest-neighbour circuits, where the
     // greedy choice takes one or two layers of a window's gates per pass.
     const uint64_t low = (m >= 64) ? ~0ull : ((1ull << m) - 1);
+    auto tile_ok = [&](int gi) { return tileable(G[gi]); };
+    auto no_took = [](int) {};
     auto dense_count = [&](const std::vector<int>& t) {
       int c = 0;
       for (int gi : t) c += !G[gi].diagonal;
@@ -175,7 +472,7 @@ static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
     uint64_t Q = low;
     std::vector<int> taken, rest = pending;
     greedy(G, &rest, &Q, L, [](const HostGate& g) { return g.dense(); },
-           tileable, &taken);
+           tile_ok, &taken, no_took);
     int best = dense_count(taken);
     for (int s0 = m; s0 + (L - m) <= n && L > m; ++s0) {
       uint64_t W = low;
@@ -183,7 +480,7 @@ static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
       std::vector<int> t2, r2 = pending;
       uint64_t W2 = W;
       greedy(G, &r2, &W2, L, [](const HostGate& g) { return g.dense(); },
-             tileable, &t2);
+             tile_ok, &t2, no_took);
       const int c = dense_count(t2);
       if (c > best) {
         best = c;
@@ -212,9 +509,27 @@ static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
     // that the low bits index lanes (contiguous HBM runs across lanes) and a
     // segment that needs few bits tends to match the I/O layout (register
     // bits L-RB..L-1), which saves the re-layout on entry or exit.
-    auto build_segs = [&](bool seed_io) {
+    // Two-qubit diagonal gates whose owner (the side whose next gate takes
+    // it, chosen as if there were no segments) should keep that gate no
+    // later than the other side's: with `keep_owners`, a gate waits for the
+    // owners' gates it must follow (`after`).
+    std::vector<std::vector<int>> after;
+    {
+      const PassOrder po(G, taken);
+      std::vector<int> shared;
+      const std::vector<int> owner = choose_owners(po, nullptr, &shared);
+      for (int d : shared) {
+        const int ua = po.next_on(owner[d], d),
+                  ub = po.next_on(po.other(d, owner[d]), d);
+        if (ua < 0 || ub < 0) continue;
+        if (after.empty()) after.resize(G.size());
+        after[size_t(po.order[ub])].push_back(po.order[ua]);
+      }
+    }
+    auto build_segs = [&](bool seed_io, bool keep_owners) {
       std::vector<Pass::Seg> segs;
       std::vector<int> seg_pending = taken;
+      std::vector<char> placed(keep_owners && !after.empty() ? G.size() : 0, 0);
       bool first = true;
       while (!seg_pending.empty()) {
         // seed_io: the first segment takes the I/O layout's register bits
@@ -222,11 +537,37 @@ static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
         uint64_t S = (first && seed_io) ? ((1ull << RB) - 1) << (L - RB) : 0;
         first = false;
         std::vector<int> seg_gates;
-        greedy(G, &seg_pending, &S, RB,
-               [&](const HostGate& g) -> uint64_t {
-                 return g.diagonal ? 0 : (1ull << local_of[g.t[0]]);
-               },
-               [](const HostGate&) { return true; }, &seg_gates);
+        auto need = [&](const HostGate& g) -> uint64_t {
+          return g.diagonal ? 0 : (1ull << local_of[g.t[0]]);
+        };
+        if (placed.empty()) {
+          greedy(G, &seg_pending, &S, RB, need, [](int) { return true; },
+                 &seg_gates, [](int) {});
+        } else {
+          greedy(G, &seg_pending, &S, RB, need,
+                 [&](int gi) {
+                   for (int ga : after[size_t(gi)])
+                     if (!placed[size_t(ga)]) return false;
+                   return true;
+                 },
+                 &seg_gates, [&](int gi) { placed[size_t(gi)] = 1; });
+          bool any_dense = false;
+          for (int gi : seg_gates) any_dense |= !G[gi].diagonal;
+          if (!any_dense && !seg_pending.empty()) {
+            // waiting gates block every remaining one: drop the waits
+            placed.clear();
+            seg_pending.insert(seg_pending.begin(), seg_gates.begin(),
+                               seg_gates.end());
+            std::vector<int> keep_order;
+            for (int gi : taken)
+              if (std::find(seg_pending.begin(), seg_pending.end(), gi) !=
+                  seg_pending.end())
+                keep_order.push_back(gi);
+            seg_pending.swap(keep_order);
+            first = segs.empty();
+            continue;
+          }
+        }
         for (int lb = L - 1; lb >= 0 && popc(S) < RB; --lb) S |= 1ull << lb;
         Pass::Seg sg;
         for (int lb = 0, j = 0; lb < L; ++lb)
@@ -250,11 +591,37 @@ static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
         r += !same(segs[i], segs[i - 1].reg_bits);
       return r;
     };
-    // the plain scan, or the seeded one where it needs fewer re-layouts
-    p.segs = build_segs(false);
+    // ops the emitted program would hold
+    auto op_count = [&](const std::vector<Pass::Seg>& segs) -> double {
+      Pass t = p;
+      t.segs = segs;
+      for (const auto& sg : segs)
+        t.gates.insert(t.gates.end(), sg.gates.begin(), sg.gates.end());
+      std::vector<TilePass> tp;
+      std::vector<TileSeg> ts;
+      std::vector<TileOp> to;
+      TileEmitStats st;
+      if (!emit_tile_pass(t, G, RB, &tp, &ts, &to, &st).empty()) return 1e30;
+      return double(st.ops);
+    };
+    // Of the plain and the I/O-seeded scans, with and without the owners'
+    // waits: the fewest ops plus, per re-layout, half an op for complex64
+    // and a whole one for complex128 (a re-layout moves every amplitude's
+    // bytes through LDS twice; the weights are the best of 0.5, 1 and 2
+    // measured on the 30-, 33- and 34-qubit circuits).
+    const double relayout_ops = 0.5 * double(b) / 8.0;
+    p.segs = build_segs(false, false);
     if (!p.segs.empty()) {
-      std::vector<Pass::Seg> seeded = build_segs(true);
-      if (relayouts(seeded) < relayouts(p.segs)) p.segs.swap(seeded);
+      double best = op_count(p.segs) + relayout_ops * relayouts(p.segs);
+      for (int v = 1; v < 4; ++v) {
+        if ((v & 2) && after.empty()) continue;
+        std::vector<Pass::Seg> alt = build_segs(v & 1, (v & 2) != 0);
+        const double c = op_count(alt) + relayout_ops * relayouts(alt);
+        if (c < best) {
+          best = c;
+          p.segs.swap(alt);
+        }
+      }
     }
     for (const auto& sg : p.segs)
       p.gates.insert(p.gates.end(), sg.gates.begin(), sg.gates.end());
@@ -281,7 +648,8 @@ static void plan_fused(const std::vector<HostGate>& G, int n, int b,
     uint64_t S = 0;
     std::vector<int> taken;
     greedy(G, &pending, &S, K,
-           [](const HostGate& g) { return g.touch(); }, fits, &taken);
+           [](const HostGate& g) { return g.touch(); },
+           [&](int gi) { return fits(G[gi]); }, &taken, [](int) {});
     Pass p;
     p.kind = kPassFused;
     p.qubits = S;
@@ -402,268 +770,6 @@ static bool is_identity2(const double* m) {
   for (int i = 0; i < 8; ++i)
     if (m[i] != id[i]) return false;
   return true;
-}
-
-// Which op absorbs a two-qubit diagonal gate (a CZ, say) decides how many
-// one-target gates merge: the gates on qubit a before and after a CZ(a, b)
-// fuse into one op muxed by b, but only one of a and b can take the CZ (the
-// other's op then reads a or b in the middle of its run).  The emitter
-// below gives a pending diagonal gate to the first dense gate processed
-// that touches it, so the processing order inside a segment is the lever.
-//
-// Model, per pass and per qubit q: the dense one-target gates on q in
-// order; a diagonal gate on q and one other qubit b is "owned" by the side
-// whose next gate absorbs it (forced when only one side has a later gate in
-// the pass, or when the two next gates lie in different register segments:
-// the earlier segment's takes it), and is then a read of b attached to q's
-// next gate.  A diagonal
-// gate owned by the other side, or a dense gate with q as a control,
-// between two gates on q keeps them apart.  Gates on q join into one op
-// when nothing keeps them apart and the reads attached to them are all of
-// one qubit b, with no dense gate on b between the reads.  The most joins
-// on a qubit under a given ownership is a small dynamic program over its
-// gates; the ownership of each shared diagonal gate is improved by local
-// search (flip while the two qubits' joins grow) from two starts, the
-// lower qubit owning every shared gate and the higher one.  Each segment is
-// then put in a commuting order (a topological order of its gates, earliest
-// first) where the owner's next gate comes before the other qubit's.  The
-// emitter still checks every merge itself: the order changes op counts,
-// never results.
-static std::vector<std::vector<int>> merge_order(
-    const Pass& p, const std::vector<HostGate>& G) {
-  std::vector<int> order, seg_of;
-  std::vector<std::vector<int>> out(p.segs.size());
-  for (size_t si = 0; si < p.segs.size(); ++si) {
-    out[si] = p.segs[si].gates;
-    for (int gi : p.segs[si].gates) {
-      order.push_back(gi);
-      seg_of.push_back(int(si));
-    }
-  }
-  const int N = int(order.size());
-  std::vector<int> target(N);
-  // per qubit (compressed rows): the positions of the gates touching it,
-  // and of the dense gates on it as target
-  std::array<int, 65> eo, to;
-  eo.fill(0);
-  to.fill(0);
-  for (int i = 0; i < N; ++i) {
-    const HostGate& g = G[order[i]];
-    target[i] = (!g.diagonal && g.k == 1) ? g.t[0] : -1;
-    for (uint64_t m = g.touch(); m; m &= m - 1) ++eo[__builtin_ctzll(m) + 1];
-    if (target[i] >= 0) ++to[target[i] + 1];
-  }
-  for (int q = 0; q < 64; ++q) {
-    eo[q + 1] += eo[q];
-    to[q + 1] += to[q];
-  }
-  std::vector<int> ev(eo[64]), tp(to[64]);
-  {
-    std::array<int, 64> fe, ft;
-    std::copy(eo.begin(), eo.begin() + 64, fe.begin());
-    std::copy(to.begin(), to.begin() + 64, ft.begin());
-    for (int i = 0; i < N; ++i) {
-      for (uint64_t m = G[order[i]].touch(); m; m &= m - 1)
-        ev[fe[__builtin_ctzll(m)]++] = i;
-      if (target[i] >= 0) tp[ft[target[i]]++] = i;
-    }
-  }
-  // dense gates on target b before position i
-  auto version = [&](int b, int i) {
-    return int(std::lower_bound(tp.begin() + to[b], tp.begin() + to[b + 1], i) -
-               (tp.begin() + to[b]));
-  };
-  // next position after i with a dense gate on target q (-1: none)
-  auto next_on = [&](int q, int i) {
-    auto it = std::upper_bound(tp.begin() + to[q], tp.begin() + to[q + 1], i);
-    return it == tp.begin() + to[q + 1] ? -1 : *it;
-  };
-  // two-qubit diagonal gates either side could absorb; forced owners
-  std::vector<int> owner(N, -1), shared;
-  for (int d = 0; d < N; ++d) {
-    const HostGate& g = G[order[d]];
-    if (!g.diagonal) continue;
-    const uint64_t tm = g.touch();
-    if (popc(tm) == 1) {
-      owner[d] = __builtin_ctzll(tm);
-    } else if (popc(tm) == 2) {
-      const int a = __builtin_ctzll(tm), b = 63 - __builtin_clzll(tm);
-      // the earlier segment's gate absorbs it; in one segment, either
-      const int na = next_on(a, d), nb = next_on(b, d);
-      if (na >= 0 && nb >= 0 && seg_of[na] == seg_of[nb]) shared.push_back(d);
-      else if (na >= 0 && (nb < 0 || seg_of[na] < seg_of[nb])) owner[d] = a;
-      else if (nb >= 0) owner[d] = b;
-    }
-  }
-  if (shared.empty()) return out;
-  // the most joins on qubit q under `owner`
-  auto joins = [&](int q) -> int {
-    int bn = -1, bm = -1, mq = -1, mv = -1;  // best per op state
-    bool first = true, apart = false, prev_plain = false;
-    int rq = -1, rv = -1;
-    bool rbad = false;
-    auto read = [&](int b, int v) {
-      if (rq < 0) {
-        rq = b;
-        rv = v;
-      } else if (rq != b || rv != v) {
-        rbad = true;
-      }
-    };
-    for (int e = eo[q]; e < eo[q + 1]; ++e) {
-      const int i = ev[e];
-      const HostGate& g = G[order[i]];
-      if (target[i] != q) {
-        if (!g.diagonal || owner[i] != q || popc(g.touch()) > 2) {
-          apart = true;  // q is read by another op, or the gate stands apart
-        } else if (popc(g.touch()) == 2) {
-          const int b = __builtin_ctzll(g.touch() & ~(uint64_t(1) << q));
-          read(b, version(b, i));
-        }
-        continue;
-      }
-      const bool plain = g.c > 1;
-      if (g.c == 1) read(g.ctl[0], version(g.ctl[0], i));
-      if (rbad || plain) {  // the reads are emitted apart from the gate
-        apart = true;
-        rq = rv = -1;
-        if (g.c == 1) {
-          rq = g.ctl[0];
-          rv = version(rq, i);
-        }
-      }
-      const bool join = !first && !apart && !plain && !prev_plain;
-      const int top = std::max(bn, bm);
-      if (first) {
-        bn = rq < 0 ? 0 : -1;
-        bm = rq < 0 ? -1 : 0;
-        mq = rq;
-        mv = rv;
-      } else if (rq < 0) {
-        const int nn = std::max(top, join && bn >= 0 ? bn + 1 : -1);
-        bm = join && bm >= 0 ? bm + 1 : -1;
-        bn = nn;
-      } else {
-        int nm = top;
-        if (join && bn >= 0) nm = std::max(nm, bn + 1);
-        if (join && bm >= 0 && mq == rq && mv == rv) nm = std::max(nm, bm + 1);
-        bm = nm;
-        bn = -1;
-        mq = rq;
-        mv = rv;
-      }
-      if (plain) {  // a controlled op stands alone
-        bn = std::max(bn, bm);
-        bm = -1;
-      }
-      first = false;
-      apart = false;
-      prev_plain = plain;
-      rq = rv = -1;
-      rbad = false;
-    }
-    return std::max(0, std::max(bn, bm));
-  };
-  auto other = [&](int d, int q) {
-    return __builtin_ctzll(G[order[d]].touch() & ~(uint64_t(1) << q));
-  };
-  std::vector<int> best_owner;
-  int best_total = -1;
-  for (int start = 0; start < 2; ++start) {
-    for (int d : shared) {
-      const uint64_t tm = G[order[d]].touch();
-      owner[d] = start == 0 ? __builtin_ctzll(tm) : 63 - __builtin_clzll(tm);
-    }
-    std::array<int, 64> jq;
-    jq.fill(0);
-    int total = 0;
-    for (int q = 0; q < 64; ++q)
-      if (eo[q + 1] > eo[q]) total += (jq[q] = joins(q));
-    for (int round = 0; round < 8; ++round) {
-      bool better = false;
-      for (int d : shared) {
-        const int a = owner[d], b = other(d, a);
-        owner[d] = b;
-        const int ja = joins(a), jb = joins(b);
-        if (ja + jb > jq[a] + jq[b]) {
-          total += ja + jb - jq[a] - jq[b];
-          jq[a] = ja;
-          jq[b] = jb;
-          better = true;
-        } else {
-          owner[d] = a;
-        }
-      }
-      if (!better) break;
-    }
-    if (total > best_total) {
-      best_total = total;
-      best_owner = owner;
-    }
-  }
-  owner.swap(best_owner);
-  // per segment: dependency edges (gates that do not commute keep their
-  // order: per qubit, a dense gate after everything since the previous
-  // dense gate, anything else after the previous dense gate) plus "owner's
-  // next gate first" edges; Kahn's algorithm taking the earliest ready
-  // gate; a cycle keeps the segment's order
-  std::vector<std::vector<int>> first_of(N);
-  for (int d : shared) {
-    const int ua = next_on(owner[d], d), ub = next_on(other(d, owner[d]), d);
-    if (ua > ub && seg_of[ua] == seg_of[ub]) first_of[ua].push_back(ub);
-  }
-  int lo = 0;
-  for (size_t si = 0; si < p.segs.size(); ++si) {
-    const int m = int(p.segs[si].gates.size()), hi = lo + m;
-    bool any = false;
-    for (int i = lo; i < hi && !any; ++i) any = !first_of[i].empty();
-    if (any) {
-      std::vector<std::vector<int>> succ(m);
-      std::vector<int> indeg(m, 0);
-      auto edge = [&](int i, int j) {
-        succ[i].push_back(j);
-        ++indeg[j];
-      };
-      std::array<int, 64> last_dense;
-      last_dense.fill(-1);
-      std::array<std::vector<int>, 64> since;
-      for (int j = 0; j < m; ++j) {
-        const HostGate& g = G[order[lo + j]];
-        for (uint64_t t = g.touch(); t; t &= t - 1) {
-          const int q = __builtin_ctzll(t);
-          if (last_dense[q] >= 0) edge(last_dense[q], j);
-          if (g.dense() >> q & 1) {
-            for (int i : since[q]) edge(i, j);
-            since[q].clear();
-            last_dense[q] = j;
-          } else {
-            since[q].push_back(j);
-          }
-        }
-      }
-      for (int i = lo; i < hi; ++i)
-        for (int j : first_of[i]) edge(i - lo, j - lo);
-      std::vector<int> res;
-      std::vector<int> heap;  // min-heap of ready local indices
-      for (int i = 0; i < m; ++i)
-        if (indeg[i] == 0) heap.push_back(i);
-      std::make_heap(heap.begin(), heap.end(), std::greater<int>());
-      while (!heap.empty()) {
-        std::pop_heap(heap.begin(), heap.end(), std::greater<int>());
-        const int i = heap.back();
-        heap.pop_back();
-        res.push_back(order[lo + i]);
-        for (int j : succ[i])
-          if (--indeg[j] == 0) {
-            heap.push_back(j);
-            std::push_heap(heap.begin(), heap.end(), std::greater<int>());
-          }
-      }
-      if (int(res.size()) == m) out[si] = std::move(res);
-    }
-    lo = hi;
-  }
-  return out;
 }
 
 std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,

@@ -137,16 +137,17 @@ def test_tiled_program_size_30q_layered():
     program and its register segments are what the tile kernel's time
     follows (one HBM round trip, the tile's load and store and its re-layouts
     per pass, about 0.2 ms per dense op per 2^30 amplitudes), so none may
-    grow.  Reached: 22 tile passes, 103 segments, 773 ops (tile qubits taken
+    grow.  Reached: 22 tile passes, 150 segments, 688 ops (tile qubits taken
     as the window of consecutive qubits that holds the most gates: 53 passes
-    and 699 ops with the first qubits the gates ask for; U3s merged, CZs
-    folded as mux ops, lone U3s deferred into the next op on their qubit,
-    each CZ given to the side where it joins the most gates)."""
+    with the first qubits the gates ask for; U3s merged, CZs folded as mux
+    ops, lone U3s deferred into the next op on their qubit, each CZ given to
+    the side where it joins the most gates, and register segments built so
+    that the side's gate comes first: 103 segments and 773 ops without)."""
     circ = qsv.Circuit.from_gates(layered_circuit(30, 40, 30))
     st = qsv.plan_program_stats(circ, 30, qsv.QSV_C64)
     assert st["passes"] == st["tile_passes"] <= 22
-    assert st["segments"] <= 103
-    assert 0 < st["tile_ops"] <= 773
+    assert st["segments"] <= 150
+    assert 0 < st["tile_ops"] <= 688
 
 
 # --------------------------------------------------------------------------
