@@ -107,6 +107,7 @@ static void greedy(const std::vector<HostGate>& G, std::vector<int>* pending,
                    uint64_t* set, int capacity, Need need, Ok ok,
                    std::vector<int>* taken, Took took) {
   std::vector<int> rest;
+  rest.reserve(pending->size());
   uint64_t blk_touch = 0, blk_dense = 0;
   for (int gi : *pending) {
     const HostGate& g = G[gi];
@@ -219,7 +220,8 @@ struct PassOrder {
 // segments goes to the earlier segment's side.
 static std::vector<int> choose_owners(const PassOrder& po,
                                       const std::vector<int>* seg_of,
-                                      std::vector<int>* shared) {
+                                      std::vector<int>* shared,
+                                      int* joined = nullptr) {
   const std::vector<HostGate>& G = po.G;
   const int N = po.size();
   std::vector<int> owner(N, -1);
@@ -240,7 +242,6 @@ static std::vector<int> choose_owners(const PassOrder& po,
       else if (nb >= 0) owner[d] = b;
     }
   }
-  if (shared->empty()) return owner;
   // the most joins on qubit q under `owner`
   auto joins = [&](int q) -> int {
     int bn = -1, bm = -1, mq = -1, mv = -1;  // best per op state
@@ -309,6 +310,14 @@ static std::vector<int> choose_owners(const PassOrder& po,
     }
     return std::max(0, std::max(bn, bm));
   };
+  if (shared->empty()) {
+    if (joined) {
+      *joined = 0;
+      for (int q = 0; q < 64; ++q)
+        if (po.eo[q + 1] > po.eo[q]) *joined += joins(q);
+    }
+    return owner;
+  }
   std::vector<int> best_owner;
   int best_total = -1;
   for (int start = 0; start < 2; ++start) {
@@ -343,6 +352,7 @@ static std::vector<int> choose_owners(const PassOrder& po,
       best_owner = owner;
     }
   }
+  if (joined) *joined = best_total;
   return best_owner;
 }
 
@@ -473,21 +483,35 @@ static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
     std::vector<int> taken, rest = pending;
     greedy(G, &rest, &Q, L, [](const HostGate& g) { return g.dense(); },
            tile_ok, &taken, no_took);
-    int best = dense_count(taken);
+    int best = dense_count(taken), best_s0 = -1;
     for (int s0 = m; s0 + (L - m) <= n && L > m; ++s0) {
+      // the dense gates a fixed window takes (the greedy scan, counting)
       uint64_t W = low;
       for (int q = s0; q < s0 + L - m; ++q) W |= uint64_t(1) << q;
-      std::vector<int> t2, r2 = pending;
-      uint64_t W2 = W;
-      greedy(G, &r2, &W2, L, [](const HostGate& g) { return g.dense(); },
-             tile_ok, &t2, no_took);
-      const int c = dense_count(t2);
+      uint64_t blk_touch = 0, blk_dense = 0;
+      int c = 0;
+      for (int gi : pending) {
+        const HostGate& g = G[gi];
+        if (!(g.dense() & blk_touch) && !(g.touch() & blk_dense) &&
+            tileable(g) && !(g.dense() & ~W)) {
+          c += !g.diagonal;
+        } else {
+          blk_touch |= g.touch();
+          blk_dense |= g.dense();
+        }
+      }
       if (c > best) {
         best = c;
-        Q = W2;
-        taken.swap(t2);
-        rest.swap(r2);
+        best_s0 = s0;
       }
+    }
+    if (best_s0 >= 0) {
+      Q = low;
+      for (int q = best_s0; q < best_s0 + L - m; ++q) Q |= uint64_t(1) << q;
+      taken.clear();
+      rest = pending;
+      greedy(G, &rest, &Q, L, [](const HostGate& g) { return g.dense(); },
+             tile_ok, &taken, no_took);
     }
     pending.swap(rest);
     // Fill the tile's qubit set up to exactly L qubits (lowest free first).
@@ -591,18 +615,21 @@ static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
         r += !same(segs[i], segs[i - 1].reg_bits);
       return r;
     };
-    // ops the emitted program would hold
+    // ops the emitted program would hold, as the ownership model counts
+    // them: one-target gates less the joins it finds
     auto op_count = [&](const std::vector<Pass::Seg>& segs) -> double {
-      Pass t = p;
-      t.segs = segs;
-      for (const auto& sg : segs)
-        t.gates.insert(t.gates.end(), sg.gates.begin(), sg.gates.end());
-      std::vector<TilePass> tp;
-      std::vector<TileSeg> ts;
-      std::vector<TileOp> to;
-      TileEmitStats st;
-      if (!emit_tile_pass(t, G, RB, &tp, &ts, &to, &st).empty()) return 1e30;
-      return double(st.ops);
+      std::vector<int> order, seg_of;
+      for (size_t si = 0; si < segs.size(); ++si)
+        for (int gi : segs[si].gates) {
+          order.push_back(gi);
+          seg_of.push_back(int(si));
+        }
+      const PassOrder po(G, std::move(order));
+      int ones = 0, joined = 0;
+      for (int t : po.target) ones += t >= 0;
+      std::vector<int> shared;
+      choose_owners(po, &seg_of, &shared, &joined);
+      return double(ones - joined);
     };
     // Of the plain and the I/O-seeded scans, with and without the owners'
     // waits: the fewest ops plus, per re-layout, half an op for complex64
