@@ -23,6 +23,11 @@ namespace qsv {
 
 static inline int popc(uint64_t x) { return __builtin_popcountll(x); }
 
+// Below this width a circuit's tile passes take microseconds, less than the
+// ownership search would cost; the batch engine steers every variant (its
+// plan serves thousands of runs).
+constexpr int kSteerMinQubits = 16;
+
 std::string resolve_options(int n, int bytes_per_amp, const int* v,
                             PlanOptions* o) {
   PlanOptions r;
@@ -42,7 +47,7 @@ std::string resolve_options(int n, int bytes_per_amp, const int* v,
     return "tile_log2 - reg_log2 must be <= 9 (512 threads per tile)";
   if (bytes_per_amp == 16 && r.reg_log2 > 4)
     return "reg_log2 must be 4 for complex128 (register budget)";
-  (void)n;
+  r.steer = n >= kSteerMinQubits;
   *o = r;
   return "";
 }
@@ -538,7 +543,8 @@ static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
     // later than the other side's: with `keep_owners`, a gate waits for the
     // owners' gates it must follow (`after`).
     std::vector<std::vector<int>> after;
-    {
+    p.steer = o.steer;
+    if (o.steer) {
       const PassOrder po(G, taken);
       std::vector<int> shared;
       const std::vector<int> owner = choose_owners(po, nullptr, &shared);
@@ -638,7 +644,11 @@ static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
     // measured on the 30-, 33- and 34-qubit circuits).
     const double relayout_ops = 0.5 * double(b) / 8.0;
     p.segs = build_segs(false, false);
-    if (!p.segs.empty()) {
+    if (!p.segs.empty() && !o.steer) {
+      // the plain scan, or the seeded one where it needs fewer re-layouts
+      std::vector<Pass::Seg> seeded = build_segs(true, false);
+      if (relayouts(seeded) < relayouts(p.segs)) p.segs.swap(seeded);
+    } else if (!p.segs.empty()) {
       double best = op_count(p.segs) + relayout_ops * relayouts(p.segs);
       for (int v = 1; v < 4; ++v) {
         if ((v & 2) && after.empty()) continue;
@@ -1148,7 +1158,12 @@ std::string emit_tile_pass(const Pass& p, const std::vector<HostGate>& G,
     return m;
   };
   std::vector<int> pend;
-  const std::vector<std::vector<int>> seg_order = merge_order(p, G);
+  std::vector<std::vector<int>> seg_order;
+  if (p.steer) {
+    seg_order = merge_order(p, G);
+  } else {
+    for (const auto& sg : p.segs) seg_order.push_back(sg.gates);
+  }
   for (size_t si = 0; si < p.segs.size(); ++si) {
     const auto& sg = p.segs[si];
     TileSeg ts = {};

@@ -40,6 +40,7 @@ struct Pass {
     std::vector<int> gates;
   };
   std::vector<Seg> segs;
+  bool steer = false;           // order segments for ownership (see above)
   // fused
   int32_t fk = 0;
   int32_t fq[8] = {0};
@@ -51,6 +52,11 @@ struct PlanOptions {
   int k_max = 5;
   int low_qubits = 4;
   int reg_log2 = 4;
+  // Spend planning time on fewer tile ops (each two-qubit diagonal gate
+  // given to the side where it joins the most gates, segments built and
+  // ordered for it).  Worth it where the plan's run time dwarfs the
+  // planning: from 16 qubits, and for batches.
+  bool steer = true;
 };
 
 struct Plan {

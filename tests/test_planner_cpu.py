@@ -247,15 +247,16 @@ def _brick_cp(n, depth, seed):
     dict(tile_log2=8, low_qubits=2)])
 @pytest.mark.parametrize("name,n,make", [
     ("layered16", 16, lambda: layered_circuit(16, 12, 8)),
-    ("brick_cp15", 15, lambda: _brick_cp(15, 14, 9)),
-    ("brick_cp13_deep", 13, lambda: _brick_cp(13, 30, 10)),
+    ("brick_cp16", 16, lambda: _brick_cp(16, 14, 9)),
+    ("brick_cp16_deep", 16, lambda: _brick_cp(16, 24, 10)),
 ])
 def test_steered_merges_match_oracle(name, n, make, opts):
-    """Brick-wall circuits whose two-qubit diagonal gates could go to either
-    neighbour: the tile program, with each such gate given to the side where
-    it joins the most one-target gates and the segments reordered to match,
-    executed on the host, against the oracle; and it has fewer ops than
-    one per one-target gate."""
+    """Brick-wall circuits (16 qubits: the planner steers from there)
+    whose two-qubit diagonal gates could go to either neighbour: the tile
+    program, with each such gate given to the side where it joins the most
+    one-target gates and the segments built and ordered to match, executed
+    on the host, against the oracle; and it has fewer ops than one per
+    one-target gate."""
     gates = make()
     v = random_state(n, 11)
     want = oracle.simulate(n, gates, init=v)
@@ -335,6 +336,29 @@ def test_emulated_random_programs_random_options(seed):
     rng = np.random.default_rng(7000 + seed)
     n = int(rng.integers(6, 15))
     gl = random_gates(n, int(rng.integers(20, 160)), rng)
+    o = random_opts(rng, False)
+    o["strategy"] = qsv.PLAN_TILED
+    circ = qsv.Circuit()
+    want = random_state(n, seed)
+    v = want.copy()
+    for u, t, c in gl:
+        circ.add(t, u, c)
+        want = oracle.apply_gate(want, n, np.asarray(u, complex), t, c)
+    got = qsv.debug_emulate_tiled(circ, n, v, qsv.fuse_opts(**o))
+    scale = max(1.0, float(np.max(np.abs(want))))
+    assert np.max(np.abs(got - want)) / scale < 1e-12, o
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_emulated_random_programs_steered(seed):
+    """Random gate lists of every accepted form on 16 qubits (from there
+    the planner builds and orders segments for diagonal-gate ownership)
+    under random tile options, tile program run on the host, against the
+    oracle."""
+    from diag_programs import random_gates, random_opts
+    rng = np.random.default_rng(9100 + seed)
+    n = 16
+    gl = random_gates(n, int(rng.integers(80, 200)), rng)
     o = random_opts(rng, False)
     o["strategy"] = qsv.PLAN_TILED
     circ = qsv.Circuit()
