@@ -89,10 +89,98 @@ __device__ __forceinline__ void pair2x2(C& x0, C& x1, T m0r, T m0i, T m1r,
   }
 }
 
+// A 2x2 FP32 matrix for the complex64 pair update, with the negated
+// imaginary part of each entry beside it.  Multiplies and two-operand FMAs
+// (VOP2 encoding) whose operands are all vector registers issue at twice
+// the rate of the same instructions reading a scalar register or carrying
+// a negation on this chip, so the cross terms take their factors from
+// vector registers: an op copies its uniform matrix there once (ten moves)
+// and each pair's twelve cross terms run at the double rate.  The diagonal
+// entries' real parts (m[0], m[6]) feed only the four three-operand FMAs,
+// which run at the single rate either way; for a uniform matrix (SM) they
+// stay in scalar registers, which keeps the tile kernel at six waves per
+// SIMD.
+struct VMat32 {
+  float m[8];  // as pair2x2's m0r..m3i
+  float n[4];  // -m[1], -m[3], -m[5], -m[7]
+};
+
+template <bool SM>
+__device__ __forceinline__ VMat32 vmat32(const float* m) {
+  VMat32 v;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    v.m[e] = m[e];
+    if (!SM || (e != 0 && e != 6)) asm volatile("" : "+v"(v.m[e]));
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v.n[k] = -m[2 * k + 1];
+    asm volatile("" : "+v"(v.n[k]));
+  }
+  return v;
+}
+
+// The pair update of pair2x2 with the cross-term factors in vector
+// registers: the same products and fused sums in the same order (a negated
+// factor gives the exactly negated product), so the results are bitwise
+// those of pair2x2; the twelve cross terms are VOP2 instructions, the four
+// own terms stay three-operand FMAs that write the amplitude registers in
+// place.
+#define QSV_PAIR_F32V(DC)                                                     \
+  asm volatile(                                                               \
+      "v_mul_f32_e32 %[t0], %[n0], %[b]\n\t"                                  \
+      "v_mul_f32_e32 %[t1], %[m1], %[a]\n\t"                                  \
+      "v_mul_f32_e32 %[t2], %[m4], %[a]\n\t"                                  \
+      "v_mul_f32_e32 %[t3], %[m4], %[b]\n\t"                                  \
+      "v_fmac_f32_e32 %[t0], %[m2], %[c]\n\t"                                 \
+      "v_fmac_f32_e32 %[t1], %[m2], %[d]\n\t"                                 \
+      "v_fmac_f32_e32 %[t2], %[n2], %[b]\n\t"                                 \
+      "v_fmac_f32_e32 %[t3], %[m5], %[a]\n\t"                                 \
+      "v_fmac_f32_e32 %[t0], %[n1], %[d]\n\t"                                 \
+      "v_fmac_f32_e32 %[t1], %[m3], %[c]\n\t"                                 \
+      "v_fmac_f32_e32 %[t2], %[n3], %[d]\n\t"                                 \
+      "v_fmac_f32_e32 %[t3], %[m7], %[c]\n\t"                                 \
+      "v_fma_f32 %[a], %[m0], %[a], %[t0]\n\t"                                \
+      "v_fma_f32 %[b], %[m0], %[b], %[t1]\n\t"                                \
+      "v_fma_f32 %[c], %[m6], %[c], %[t2]\n\t"                                \
+      "v_fma_f32 %[d], %[m6], %[d], %[t3]"                                     \
+      : [a] "+v"(x0.x), [b] "+v"(x0.y), [c] "+v"(x1.x), [d] "+v"(x1.y),     \
+        [t0] "=&v"(t0), [t1] "=&v"(t1), [t2] "=&v"(t2), [t3] "=&v"(t3)        \
+      : [m0] DC(v.m[0]), [m1] "v"(v.m[1]), [m2] "v"(v.m[2]),                  \
+        [m3] "v"(v.m[3]), [m4] "v"(v.m[4]), [m5] "v"(v.m[5]),                 \
+        [m6] DC(v.m[6]), [m7] "v"(v.m[7]), [n0] "v"(v.n[0]),                  \
+        [n1] "v"(v.n[1]), [n2] "v"(v.n[2]), [n3] "v"(v.n[3]))
+
+template <bool SM, typename C>
+__device__ __forceinline__ void pair2x2v(C& x0, C& x1, const VMat32& v) {
+  float t0, t1, t2, t3;
+  if constexpr (SM) QSV_PAIR_F32V(QSV_SREG);
+  else QSV_PAIR_F32V(QSV_VREG);
+}
+
 template <int I, int R, bool CTRL, bool SM, typename C, typename T>
 __device__ __forceinline__ void dense1_regs(C* a, const T* m, uint32_t rt,
                                             const uint32_t* lr,
                                             uint32_t lctrl) {
+  if constexpr (sizeof(T) == 4) {
+    const VMat32 v = vmat32<SM>(m);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (j & (1 << I)) continue;
+      const int j1 = j | (1 << I);
+      if constexpr (CTRL) {
+        C y0 = a[j], y1 = a[j1];
+        pair2x2v<SM>(y0, y1, v);
+        const bool on = ((rt & lctrl) | (lr[j] & lctrl)) == lctrl;
+        a[j] = csel(on, y0, a[j]);
+        a[j1] = csel(on, y1, a[j1]);
+      } else {
+        pair2x2v<SM>(a[j], a[j1], v);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     if (j & (1 << I)) continue;
@@ -123,6 +211,27 @@ __device__ __forceinline__ void dense1_mux_regs(C* a, const T* m0,
                                                 const T* m1, uint32_t rt,
                                                 const uint32_t* lr,
                                                 uint32_t lctrl, int mbit) {
+  if constexpr (sizeof(T) == 4) {
+    // complex64: every pair under m0 (kept where selected), then under m1,
+    // with one matrix at a time in vector registers
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const VMat32 v = vmat32<true>(h ? m1 : m0);
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (j & (1 << I)) continue;
+        const int j1 = j | (1 << I);
+        const bool sel = (((rt >> mbit) | (lr[j] >> mbit)) & 1u) != 0;
+        const bool on = ((rt & lctrl) | (lr[j] & lctrl)) == lctrl;
+        C y0 = a[j], y1 = a[j1];
+        pair2x2v<true>(y0, y1, v);
+        const bool keep = on && (h ? sel : !sel);
+        a[j] = csel(keep, y0, a[j]);
+        a[j1] = csel(keep, y1, a[j1]);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     if (j & (1 << I)) continue;
@@ -196,6 +305,21 @@ __device__ __forceinline__ void dense1_dispatch(int reg, C* a, const T* m,
 template <int I, int K, int R, typename C, typename T>
 __device__ __forceinline__ void dense1_muxreg_regs(C* a, const T* m0,
                                                    const T* m1) {
+  if constexpr (sizeof(T) == 4) {
+    // complex64: the pairs of m0, then those of m1, one matrix at a time
+    // in vector registers
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const VMat32 v = vmat32<true>(h ? m1 : m0);
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (j & (1 << I)) continue;
+        if ((j >> K & 1) != h) continue;
+        pair2x2v<true>(a[j], a[j | (1 << I)], v);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     if (j & (1 << I)) continue;
