@@ -26,10 +26,13 @@ if ROOT not in sys.path:
 METRIC = ("gate-pass HBM GB/s (% of peak), 30q depth-40 time; "
           "batched circuits/s, p99")
 PEAK_HBM_GBPS = 8000.0
-# vector FMA issue rate of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
-# x 2.4 GHz, for FP32 without packed instructions and for FP64 alike
+# the chip's vector peaks: FP64 FMA, 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# x 2.4 GHz = 78.6 TFLOP/s; FP32 twice that, 157.3 TFLOP/s (the tile kernel's
+# complex64 cross terms are VOP2 FMAs on vector registers, which issue at
+# that double rate)
 CLOCK_HZ = 2.4e9
-PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * CLOCK_HZ / 1e12
+PEAK_VALU_F64_TFLOPS = 256 * 4 * 16 * 2 * CLOCK_HZ / 1e12
+PEAK_VALU_F32_TFLOPS = 2 * PEAK_VALU_F64_TFLOPS
 N_QUBITS, DEPTH, SEED = 30, 40, 30
 SHOTS, SAMPLE_SEED = 1_000_000, 1000003
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_kernel_30q_c64_traffic.json")
@@ -1086,11 +1089,12 @@ def main() -> int:
         # the planner's count of the arithmetic its tile ops define, per
         # launch (one step's tile passes)
         tflop = stats["tile_flops"] / max(1, stats["tile_passes"])
+        peak = (PEAK_VALU_F32_TFLOPS if prec == qsv.QSV_C64
+                else PEAK_VALU_F64_TFLOPS)
         roof = {"bound": "alu",
                 "achieved": round(tflop / (avg_ms * 1e-3) / 1e12, 2),
-                "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tflop / (avg_ms * 1e-3) / 1e12 /
-                              PEAK_VALU_TFLOPS, 4),
+                "peak": round(peak, 1), "unit": "TFLOP/s",
+                "frac": round(tflop / (avg_ms * 1e-3) / 1e12 / peak, 4),
                 "traffic": traffic,
                 "kernel": kind_names[dom],
                 "flops_per_launch": tflop,
@@ -1101,11 +1105,16 @@ def main() -> int:
                         "frac": round(achieved / PEAK_HBM_GBPS, 4),
                         "bytes_per_launch": per_launch,
                         "traffic": traffic}}
+        if counters and "SQ_INSTS_VALU_FLOPS_FP32" in counters:
+            # the FP32 flops the hardware executed per launch (the counter
+            # counts per wave64 instruction lane-flop / 64), the redundant
+            # ones of the in-place update included, over the live launch time
+            hw = counters["SQ_INSTS_VALU_FLOPS_FP32"] * 64
+            roof["hw_fp32_flops_per_launch"] = hw
+            roof["hw_fp32_TFLOPs"] = round(hw / (avg_ms * 1e-3) / 1e12, 2)
+            roof["hw_fp32_frac"] = round(
+                hw / (avg_ms * 1e-3) / 1e12 / PEAK_VALU_F32_TFLOPS, 4)
         if counters and "SQ_INSTS_VALU" in counters:
-            # wave64 VALU instructions take 4 cycles of one SIMD; 1024 SIMDs
-            roof["valu_issue_frac"] = round(
-                counters["SQ_INSTS_VALU"] * 4 /
-                (1024 * CLOCK_HZ * avg_ms * 1e-3), 4)
             roof["valu_insts_per_wave"] = round(
                 counters["SQ_INSTS_VALU"] / counters.get("SQ_WAVES", 1), 1)
     else:
