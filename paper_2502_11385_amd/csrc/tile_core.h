@@ -94,8 +94,9 @@ __device__ __forceinline__ void pair2x2(C& x0, C& x1, T m0r, T m0i, T m1r,
 // (VOP2 encoding) whose operands are all vector registers issue at twice
 // the rate of the same instructions reading a scalar register or carrying
 // a negation on this chip, so the cross terms take their factors from
-// vector registers: an op copies its uniform matrix there once (ten moves)
-// and each pair's twelve cross terms run at the double rate.  The diagonal
+// vector registers: an op copies its uniform matrix there once (six moves,
+// four of them 64-bit) and each pair's twelve cross terms run at the
+// double rate.  The diagonal
 // entries' real parts (m[0], m[6]) feed only the four three-operand FMAs,
 // which run at the single rate either way; for a uniform matrix (SM) they
 // stay in scalar registers, which keeps the tile kernel at six waves per
@@ -105,18 +106,45 @@ struct VMat32 {
   float n[4];  // -m[1], -m[3], -m[5], -m[7]
 };
 
+// Two uniform FP32 values into a vector-register pair with one 64-bit move
+// (a move from scalar registers costs the same issue time for 64 bits as
+// for 32).
+__device__ __forceinline__ void vmov2(float lo, float hi, float* vlo,
+                                      float* vhi) {
+  const uint64_t s = uint64_t(__builtin_bit_cast(uint32_t, lo)) |
+                     (uint64_t(__builtin_bit_cast(uint32_t, hi)) << 32);
+  uint64_t d;
+  asm volatile("v_mov_b64 %0, %1" : "=v"(d) : "s"(s));
+  *vlo = __builtin_bit_cast(float, uint32_t(d));
+  *vhi = __builtin_bit_cast(float, uint32_t(d >> 32));
+}
+
 template <bool SM>
 __device__ __forceinline__ VMat32 vmat32(const float* m) {
   VMat32 v;
+  if constexpr (SM) {
+    // uniform: m[2..5] and the four negations in 64-bit pairs, m[1] and
+    // m[7] alone; m[0] and m[6] stay scalar (six moves, not ten)
+    v.m[0] = m[0];
+    v.m[6] = m[6];
+    vmov2(m[2], m[3], &v.m[2], &v.m[3]);
+    vmov2(m[4], m[5], &v.m[4], &v.m[5]);
+    vmov2(-m[1], -m[3], &v.n[0], &v.n[1]);
+    vmov2(-m[5], -m[7], &v.n[2], &v.n[3]);
+    v.m[1] = m[1];
+    v.m[7] = m[7];
+    asm volatile("" : "+v"(v.m[1]), "+v"(v.m[7]));
+  } else {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    v.m[e] = m[e];
-    if (!SM || (e != 0 && e != 6)) asm volatile("" : "+v"(v.m[e]));
-  }
+    for (int e = 0; e < 8; ++e) {
+      v.m[e] = m[e];
+      asm volatile("" : "+v"(v.m[e]));
+    }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    v.n[k] = -m[2 * k + 1];
-    asm volatile("" : "+v"(v.n[k]));
+    for (int k = 0; k < 4; ++k) {
+      v.n[k] = -m[2 * k + 1];
+      asm volatile("" : "+v"(v.n[k]));
+    }
   }
   return v;
 }
