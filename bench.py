@@ -887,8 +887,8 @@ def serve_leg(qsv, n: int, saved=None) -> dict:
 # --------------------------------------------------------------- GPU leg
 
 def _copy_peak(torch, out: dict) -> float:
-    """Device-to-device copy of 4 GiB, HIP-event timed: GB/s of read +
-    write bytes, recorded in out["copy_peak"]."""
+    """The runtime's device-to-device copy of 4 GiB, HIP-event timed: GB/s
+    of read + write bytes, recorded in out["copy_peak"]."""
     csrc = torch.empty(1 << 30, dtype=torch.float32, device="cuda")
     cdst = torch.empty_like(csrc)
     csrc.fill_(1.0)
@@ -905,7 +905,8 @@ def _copy_peak(torch, out: dict) -> float:
     gbps = 2 * (4 << 30) / (copy_ms * 1e-3) / 1e9
     del csrc, cdst
     torch.cuda.empty_cache()
-    out["copy_peak"] = {"workload": "device-to-device copy of 4 GiB",
+    out["copy_peak"] = {"workload": ("runtime device-to-device copy of 4 GiB "
+                                     "(torch copy_, hipMemcpyAsync)"),
                         "ms": round(copy_ms, 3), "GBps": round(gbps, 1),
                         "frac_of_8TBps": round(gbps / PEAK_HBM_GBPS, 4)}
     return gbps
