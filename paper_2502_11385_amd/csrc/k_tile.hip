@@ -191,8 +191,9 @@ __device__ __forceinline__ void tile_body(typename CxT<T>::type* __restrict__ am
   }
 }
 
-// complex64 with 16 registers per thread: capped at 96 VGPRs so that five
-// waves share each SIMD (five 32 KiB tiles fill the CU's 160 KiB of LDS).
+// complex64 with 16 registers per thread: capped at 102 VGPRs so that at
+// least five waves share each SIMD (the build reaches 80 VGPRs, six waves;
+// the half re-layouts take 16 KiB of LDS per tile, ten tiles per CU).
 template <bool LANE32>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5)))
     tile_kernel_c64_rb4(float2* __restrict__ amp,
