@@ -38,7 +38,8 @@ std::string resolve_options(int n, int bytes_per_amp, const int* v,
   // A circuit that fits one tile runs on one work-group, bound by the
   // latency of its op chain: eight amplitudes per thread put twice the
   // waves on it (12 qubits: 158 against 188 us per circuit, complex64).
-  r.reg_log2 = (v && v[4]) ? v[4] : (n <= r.tile_log2 ? 3 : 4);
+  r.reg_log2 = (v && v[4]) ? v[4]
+                           : (n <= r.tile_log2 && r.tile_log2 <= 12 ? 3 : 4);
   if (r.strategy < 0 || r.strategy > 3) return "unknown strategy";
   if (r.tile_log2 < 8 || r.tile_log2 > 13) return "tile_log2 must be 8..13";
   if (r.k_max < 1 || r.k_max > kMaxK) return "k_max must be 1..5";

@@ -370,3 +370,21 @@ def test_emulated_random_programs_steered(seed):
     got = qsv.debug_emulate_tiled(circ, n, v, qsv.fuse_opts(**o))
     scale = max(1.0, float(np.max(np.abs(want))))
     assert np.max(np.abs(got - want)) / scale < 1e-12, o
+
+
+@pytest.mark.parametrize("n,L", [(12, 13), (12, 12), (10, 12), (13, 13),
+                                 (8, 8), (14, 12)])
+def test_default_register_count_is_valid(n, L):
+    """Circuits that fit one tile default to eight amplitudes per thread
+    where the tile allows it (at most 512 threads); every default plans."""
+    circ = qsv.Circuit.from_gates(layered_circuit(n, 4, 5))
+    for prec in (qsv.QSV_C64, qsv.QSV_C128):
+        st = qsv.plan_program_stats(circ, n, prec,
+                                    qsv.fuse_opts(strategy=qsv.PLAN_TILED,
+                                                  tile_log2=L))
+        assert st["tile_passes"] >= 1
+    v = random_state(n, 3)
+    want = oracle.simulate(n, layered_circuit(n, 4, 5), init=v)
+    if n <= 16:
+        got = qsv.debug_emulate_tiled(circ, n, v, qsv.fuse_opts(tile_log2=L))
+        assert np.max(np.abs(got - want)) < 1e-12
