@@ -106,6 +106,32 @@ def test_dense_k_targets_with_controls(prec, k, c):
 
 
 @pytest.mark.parametrize("prec", [C64, C128])
+@pytest.mark.parametrize("k,c", [(2, 0), (2, 1), (2, 2), (3, 0), (3, 1)])
+def test_dense_with_qubit0_in_every_target_slot(prec, k, c):
+    """k = 2, 3 gates with qubit 0 as each of their targets in turn (the
+    complex64 kernel moves qubit 0's adjacent amplitude pairs as one 16-byte
+    access, taking qubit 0 as the lowest matrix bit: for k = 2 the host
+    swaps the targets and the matrix bits when qubit 0 comes second),
+    with and without controls, 14 qubits, against the oracle."""
+    n = 14
+    rng = np.random.default_rng(700 + 10 * k + c)
+    v = random_state(n, 70 + k + c)
+    s = _state(n, prec, v)
+    want = v.copy()
+    for slot in range(k):
+        others = [int(q) for q in rng.choice(np.arange(1, n), k - 1 + c,
+                                             replace=False)]
+        tq = others[:k - 1]
+        tq.insert(slot, 0)
+        cq = others[k - 1:]
+        u = _random_unitary(1 << k, rng)
+        s.apply_gate(tq, u, cq)
+        want = oracle.apply_gate(want, n, u, tq, cq)
+    _check_amps(s.get(), want, prec, f"k={k} c={c}")
+    s.free()
+
+
+@pytest.mark.parametrize("prec", [C64, C128])
 @pytest.mark.parametrize("k", [4, 5])
 def test_dense_k4_k5_matrix_cores_20q(prec, k):
     """Control-free 4- and 5-target gates (the matrix-core path) on 20
