@@ -18,6 +18,8 @@
 #include <functional>
 #include <map>
 #include <tuple>
+#include <unordered_map>
+#include <unordered_set>
 
 namespace qsv {
 
@@ -546,7 +548,7 @@ static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
     // it, chosen as if there were no segments) should keep that gate no
     // later than the other side's: with `keep_owners`, a gate waits for the
     // owners' gates it must follow (`after`).
-    std::vector<std::vector<int>> after;
+    std::unordered_map<int, std::vector<int>> after;  // gate -> owners' gates
     p.steer = o.steer;
     if (o.steer) {
       const PassOrder po(G, taken);
@@ -556,14 +558,14 @@ static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
         const int ua = po.next_on(owner[d], d),
                   ub = po.next_on(po.other(d, owner[d]), d);
         if (ua < 0 || ub < 0) continue;
-        if (after.empty()) after.resize(G.size());
-        after[size_t(po.order[ub])].push_back(po.order[ua]);
+        after[po.order[ub]].push_back(po.order[ua]);
       }
     }
     auto build_segs = [&](bool seed_io, bool keep_owners) {
       std::vector<Pass::Seg> segs;
       std::vector<int> seg_pending = taken;
-      std::vector<char> placed(keep_owners && !after.empty() ? G.size() : 0, 0);
+      bool waits = keep_owners && !after.empty();
+      std::unordered_set<int> placed;
       bool first = true;
       while (!seg_pending.empty()) {
         // seed_io: the first segment takes the I/O layout's register bits
@@ -574,22 +576,24 @@ static void plan_tiled(const std::vector<HostGate>& G, int n, int b,
         auto need = [&](const HostGate& g) -> uint64_t {
           return g.diagonal ? 0 : (1ull << local_of[g.t[0]]);
         };
-        if (placed.empty()) {
+        if (!waits) {
           greedy(G, &seg_pending, &S, RB, need, [](int) { return true; },
                  &seg_gates, [](int) {});
         } else {
           greedy(G, &seg_pending, &S, RB, need,
                  [&](int gi) {
-                   for (int ga : after[size_t(gi)])
-                     if (!placed[size_t(ga)]) return false;
+                   const auto it = after.find(gi);
+                   if (it == after.end()) return true;
+                   for (int ga : it->second)
+                     if (!placed.count(ga)) return false;
                    return true;
                  },
-                 &seg_gates, [&](int gi) { placed[size_t(gi)] = 1; });
+                 &seg_gates, [&](int gi) { placed.insert(gi); });
           bool any_dense = false;
           for (int gi : seg_gates) any_dense |= !G[gi].diagonal;
           if (!any_dense && !seg_pending.empty()) {
             // waiting gates block every remaining one: drop the waits
-            placed.clear();
+            waits = false;
             seg_pending.insert(seg_pending.begin(), seg_gates.begin(),
                                seg_gates.end());
             std::vector<int> keep_order;
