@@ -886,6 +886,24 @@ def serve_leg(qsv, n: int, saved=None) -> dict:
 
 # --------------------------------------------------------------- GPU leg
 
+def _plain_bytes(gates, n: int, b: int) -> int:
+    """Algorithmic bytes of running `gates` one plain pass per gate: a
+    c-controlled dense gate reads and writes 2^(n-c) amplitudes, a CZ or a
+    controlled phase 2^(n-2), a one-qubit phase 2^(n-1)."""
+    total = 0
+    for g in gates:
+        if g.name in ("cz", "cp"):
+            m = n - 2
+        elif g.name in ("p", "s", "t", "z", "rz", "sdg", "tdg"):
+            m = n - 1
+        elif g.name in ("cx", "cy", "ch", "cu3"):
+            m = n - 1
+        else:
+            m = n
+        total += 2 * (b << m)
+    return total
+
+
 def _copy_peak(torch, out: dict) -> float:
     """The runtime's device-to-device copy of 4 GiB, HIP-event timed: GB/s
     of read + write bytes, recorded in out["copy_peak"]."""
@@ -1185,6 +1203,16 @@ def main() -> int:
         "depth40_circuit_ms": round(circuit_ms, 3),
         "gate_pass_GBps": round(gate_pass_gbps, 1),
         "gate_pass_pct_of_peak": round(100 * gate_pass_gbps / PEAK_HBM_GBPS, 1),
+        # the circuit against what it would cost as one pass per gate: gate
+        # passes per second, and the per-gate algorithmic bytes (a full pass
+        # per one-qubit gate, a quarter pass per CZ) over the circuit time
+        "effective": {
+            "gate_passes_per_s": round(len(gates) / (circuit_ms * 1e-3), 1),
+            "plain_per_gate_bytes": _plain_bytes(gates, n, b),
+            "GBps": round(_plain_bytes(gates, n, b) / (circuit_ms * 1e-3) /
+                          1e9, 1),
+            "x_of_8TBps": round(_plain_bytes(gates, n, b) /
+                                (circuit_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 2)},
         "passes": stats["passes"], "tile_segments": stats["segments"],
         "tile_ops": stats["tile_ops"],
         "plan_ms": round(stats["plan_ns"] / 1e6, 3),
