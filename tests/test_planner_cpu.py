@@ -388,3 +388,18 @@ def test_default_register_count_is_valid(n, L):
     if n <= 16:
         got = qsv.debug_emulate_tiled(circ, n, v, qsv.fuse_opts(tile_log2=L))
         assert np.max(np.abs(got - want)) < 1e-12
+
+
+def test_planner_is_deterministic():
+    """The same circuit plans to the same program every time (the steered
+    search included), so a state's bits do not depend on the call."""
+    gates = _brick_cp(16, 10, 21)
+    circ = qsv.Circuit.from_gates(gates)
+    v = random_state(16, 4)
+    o = qsv.fuse_opts()
+    a = qsv.plan_program_stats(circ, 16, qsv.QSV_C64, o)
+    b = qsv.plan_program_stats(circ, 16, qsv.QSV_C64, o)
+    assert a == b
+    x = qsv.debug_emulate_tiled(circ, 16, v, o)
+    y = qsv.debug_emulate_tiled(circ, 16, v, o)
+    assert np.array_equal(x, y)
