@@ -176,6 +176,35 @@ def test_diagonal_gates(prec):
     _check_amps(s.get(), want, prec, "diagonal")
 
 
+@pytest.mark.parametrize("prec", [C64, C128])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 13])
+def test_diagonal_gates_small_and_ragged(prec, n):
+    """Every placement of a diagonal gate's fixed and target bits on tiny
+    states (a thread's vectors run past the end of the state) and on one
+    wider than a thread's share of a work-group."""
+    rng = np.random.default_rng(40 + n)
+    v = random_state(n, 41 + n)
+    s = _state(n, prec, v)
+    want = v.copy()
+    for q in range(n):
+        u = np.diag([1, np.exp(1j * rng.uniform(0, 6))])     # masked phase
+        s.apply_gate([q], u)
+        want = oracle.apply_gate(want, n, u, [q], [])
+        u = np.diag(np.exp(1j * rng.uniform(0, 6, 2)))       # table
+        s.apply_gate([q], u)
+        want = oracle.apply_gate(want, n, u, [q], [])
+        for c in range(n):
+            if c == q:
+                continue
+            u = np.diag([1, -1])                               # CZ
+            s.apply_gate([q], u, [c])
+            want = oracle.apply_gate(want, n, u, [q], [c])
+            u = np.diag(np.exp(1j * rng.uniform(0, 6, 2)))   # controlled RZ
+            s.apply_gate([q], u, [c])
+            want = oracle.apply_gate(want, n, u, [q], [c])
+    _check_amps(s.get(), want, prec, f"diagonal n={n}")
+
+
 # ---------------------------------------------------------------- a5-a8
 
 STRATS = {
