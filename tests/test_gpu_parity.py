@@ -106,6 +106,30 @@ def test_dense_k_targets_with_controls(prec, k, c):
 
 
 @pytest.mark.parametrize("prec", [C64, C128])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_dense_with_low_controls(prec, k):
+    """Controls on the low qubits, which the complex64 kernel tests per lane
+    (writing untouched amplitudes back, or not storing them), alone, mixed
+    with one another and with higher controls, targets low and high,
+    against the oracle."""
+    n = 13
+    rng = np.random.default_rng(70 + k)
+    v = random_state(n, 71 + k)
+    s = _state(n, prec, v)
+    want = v.copy()
+    control_sets = [[0], [1], [2], [3], [4], [0, 3], [3, 6], [1, 2],
+                    [2, 9], [0, 1, 2, 3]]
+    for cs in control_sets:
+        free = [q for q in range(n) if q not in cs]
+        for ts in (free[:k], free[-k:],
+                   [int(q) for q in rng.choice(free, k, replace=False)]):
+            u = _random_unitary(1 << k, rng)
+            s.apply_gate(ts, u, cs)
+            want = oracle.apply_gate(want, n, u, ts, cs)
+        _check_amps(s.get(), want, prec, f"k={k} controls={cs}")
+
+
+@pytest.mark.parametrize("prec", [C64, C128])
 @pytest.mark.parametrize("k,c", [(2, 0), (2, 1), (2, 2), (3, 0), (3, 1)])
 def test_dense_with_qubit0_in_every_target_slot(prec, k, c):
     """k = 2, 3 gates with qubit 0 as each of their targets in turn (the
@@ -179,9 +203,9 @@ def test_diagonal_gates(prec):
 @pytest.mark.parametrize("prec", [C64, C128])
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 13])
 def test_diagonal_gates_small_and_ragged(prec, n):
-    """Every placement of a diagonal gate's fixed and target bits on tiny
-    states (a thread's vectors run past the end of the state) and on one
-    wider than a thread's share of a work-group."""
+    """Every placement of a diagonal gate's fixed and target bits, the low
+    ones tested per lane, on states smaller than one wave and on one that
+    spans many work-groups."""
     rng = np.random.default_rng(40 + n)
     v = random_state(n, 41 + n)
     s = _state(n, prec, v)
