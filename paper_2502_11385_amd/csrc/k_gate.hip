@@ -55,21 +55,38 @@ struct DenseArgs {
   const double* mptr;  // matrix for k >= 3
 };
 
-// Low fixed bits.  A pass that skips the amplitudes where a fixed bit (a
-// control, or a bit a diagonal pass needs set) is 0 walks runs of 2^p
-// amplitudes, p that bit; below a 128-byte line every line is still fetched,
-// and each wave covers its lines in part.  For such bits the lanes walk whole
-// lines and test the bits themselves.  Measured on 30-qubit passes: with runs
-// under 64 bytes, writing the untouched amplitudes back unchanged beats
-// skipping them (whole-line writes; complex64 control on qubit 0, 1 or 2:
-// 2.80 against 3.43 ms; CZ on qubit 0 or 1: 1.40 against 1.55 ms complex64,
-// 2.88 against 3.25 ms complex128); a complex64 control on qubit 3 (64-byte
-// runs) gains most by storing nothing there (2.48 against 3.03 ms).  The
-// complex128 dense kernel keeps the skipping walk: testing its controls per
-// lane gained nothing there.
-constexpr uint64_t kKeepMaskC64 = 0x7;   // dense, complex64: keep
-constexpr uint64_t kLowMaskC64 = 0xf;    // dense, complex64: keep or skip
-constexpr uint64_t kDiagMaskC64 = 0x7, kDiagMaskC128 = 0x3;
+// Low fixed bits.  A pass that visits only the amplitudes whose fixed bits
+// (controls, or the bits a diagonal pass needs set) are 1 walks runs of 2^p
+// amplitudes, p the lowest such bit; where the runs are short every line is
+// fetched anyway and each wave covers its lines in part.  For the lowest bits
+// the lanes walk whole runs and test the bits themselves, and where one is 0
+// they either store the amplitudes back unchanged (keep: whole lines are
+// written) or leave them alone (skip).  Chosen by measurement on 30-qubit
+// passes (ms, before and after):
+//   keep, runs under 64 bytes: complex64 control on qubit 0, 1 or 2,
+//     3.46 -> 2.81; complex64 CZ on qubit 0, 1 or 2, 1.57 -> 1.40;
+//     complex128 CZ on qubit 0 or 1, 3.27 -> 2.90;
+//   skip: complex64 control on qubit 3, 3.05 -> 2.47, on qubit 4,
+//     1.70 -> 1.51; CZ on qubit 3 complex64, 1.21 -> 1.17; CZ on qubit 2 or 3
+//     complex128, 3.00 -> 2.62 and 1.55 -> 1.42.
+// Not taken: skip for a complex64 CZ on qubit 4 (0.77 -> 1.10), and testing
+// higher bits beside keep ones (complex128 CZ on qubits 1, 2: 6.26 -> 6.53),
+// so a gate with bits of both kinds has only its keep bits tested.  The
+// complex128 dense kernel keeps the plain walk: neither form gained there
+// (storing back made the compiler wait on each 16-byte store).
+struct LowBits {
+  uint64_t keep, skip;
+};
+constexpr LowBits kDenseLowC64 = {0x7, 0x18};
+constexpr LowBits kDenseLowC128 = {0, 0};
+constexpr LowBits kDiagLowC64 = {0x7, 0x8};
+constexpr LowBits kDiagLowC128 = {0x3, 0xc};
+
+// The fixed bits the lanes test: the keep bits among `fixed` if any, else
+// its skip bits.
+static uint64_t lane_tested(uint64_t fixed, LowBits lb) {
+  return (fixed & lb.keep) ? fixed & lb.keep : fixed & lb.skip;
+}
 
 // How a dense pass treats the controls in args.lowmask: kLowNone has none;
 // otherwise the lanes test them and, where one is 0, store the amplitudes
@@ -170,8 +187,9 @@ static void dense_dispatch_t(void* amp, int k, unsigned blocks,
 template <typename T>
 static void dense_dispatch(void* amp, int k, unsigned blocks,
                            const DenseArgs& args, hipStream_t stream) {
-  if constexpr (sizeof(T) == 4) {
-    if (args.lowmask & kKeepMaskC64) {
+  constexpr LowBits lb = sizeof(T) == 4 ? kDenseLowC64 : kDenseLowC128;
+  if constexpr (lb.keep | lb.skip) {
+    if (args.lowmask & lb.keep) {
       dense_dispatch_t<T, kLowKeep>(amp, k, blocks, args, stream);
       return;
     }
@@ -195,7 +213,8 @@ hipError_t launch_dense(int prec, void* amp, int n, const HostGate& g,
   // 4-5 targets run on the matrix cores (launch_fused_apply)
   if (g.k > 3) return hipErrorInvalidValue;
   DenseArgs args = {};
-  args.lowmask = prec == 1 ? g.cmask & kLowMaskC64 : 0;
+  args.lowmask =
+      lane_tested(g.cmask, prec == 1 ? kDenseLowC64 : kDenseLowC128);
   args.cmask = g.cmask & ~args.lowmask;
   sorted_positions(g.tmask | args.cmask, args.pos, &args.npos);
   args.n_groups = uint64_t(1) << (n - args.npos);
@@ -251,7 +270,7 @@ struct DiagArgs {
 };
 
 // Masked phase: multiply the amplitudes whose bits in fixed_mask are all 1.
-template <typename T>
+template <typename T, bool SKIP>
 __global__ void __launch_bounds__(256)
     diag_masked_kernel(typename CxT<T>::type* __restrict__ a, DiagArgs args) {
   using C = typename CxT<T>::type;
@@ -265,12 +284,17 @@ __global__ void __launch_bounds__(256)
     for (int p = 0; p < args.npos; ++p) i = insert_zero64(i, args.pos[p]);
     i |= args.fixed_mask;
     const C v = a[i];
-    a[i] = (i & args.lowmask) == args.lowmask ? cmul(v, ph) : v;
+    const bool on = (i & args.lowmask) == args.lowmask;
+    if constexpr (SKIP) {
+      if (on) a[i] = cmul(v, ph);
+    } else {
+      a[i] = on ? cmul(v, ph) : v;
+    }
   }
 }
 
 // General diagonal: multiply by d[r(i)] where controls are satisfied.
-template <typename T>
+template <typename T, bool SKIP>
 __global__ void __launch_bounds__(256)
     diag_table_kernel(typename CxT<T>::type* __restrict__ a, DiagArgs args) {
   using C = typename CxT<T>::type;
@@ -286,7 +310,12 @@ __global__ void __launch_bounds__(256)
     f.x = T(args.d[2 * r]);
     f.y = T(args.d[2 * r + 1]);
     const C v = a[i];
-    a[i] = (i & args.lowmask) == args.lowmask ? cmul(v, f) : v;
+    const bool on = (i & args.lowmask) == args.lowmask;
+    if constexpr (SKIP) {
+      if (on) a[i] = cmul(v, f);
+    } else {
+      a[i] = on ? cmul(v, f) : v;
+    }
   }
 }
 
@@ -307,27 +336,35 @@ hipError_t launch_diag(int prec, void* amp, int n, const HostGate& g,
       args.d[2 * r + 1] = g.m[2 * (r * d + r) + 1];
     }
   }
-  args.lowmask =
-      args.fixed_mask & (prec == 1 ? kDiagMaskC64 : kDiagMaskC128);
+  const LowBits lb = prec == 1 ? kDiagLowC64 : kDiagLowC128;
+  args.lowmask = lane_tested(args.fixed_mask, lb);
+  const bool skip = args.lowmask && !(args.lowmask & lb.keep);
   args.fixed_mask &= ~args.lowmask;
   sorted_positions(args.fixed_mask, args.pos, &args.npos);
   args.n_items = uint64_t(1) << (n - args.npos);
   const unsigned blocks = grid_blocks(args.n_items, 256);
+#define QSV_DIAG(KERNEL, T)                                              \
+  do {                                                                   \
+    using C = typename CxT<T>::type;                                     \
+    if (skip)                                                            \
+      KERNEL<T, true><<<blocks, 256, 0, stream>>>(static_cast<C*>(amp),  \
+                                                  args);                 \
+    else                                                                 \
+      KERNEL<T, false><<<blocks, 256, 0, stream>>>(static_cast<C*>(amp), \
+                                                   args);                \
+  } while (0)
   if (g.masked_phase) {
     if (prec == 1)
-      diag_masked_kernel<float><<<blocks, 256, 0, stream>>>(
-          static_cast<float2*>(amp), args);
+      QSV_DIAG(diag_masked_kernel, float);
     else
-      diag_masked_kernel<double><<<blocks, 256, 0, stream>>>(
-          static_cast<double2*>(amp), args);
+      QSV_DIAG(diag_masked_kernel, double);
   } else {
     if (prec == 1)
-      diag_table_kernel<float><<<blocks, 256, 0, stream>>>(
-          static_cast<float2*>(amp), args);
+      QSV_DIAG(diag_table_kernel, float);
     else
-      diag_table_kernel<double><<<blocks, 256, 0, stream>>>(
-          static_cast<double2*>(amp), args);
+      QSV_DIAG(diag_table_kernel, double);
   }
+#undef QSV_DIAG
   return hipGetLastError();
 }
 

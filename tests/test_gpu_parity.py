@@ -117,8 +117,8 @@ def test_dense_with_low_controls(prec, k):
     v = random_state(n, 71 + k)
     s = _state(n, prec, v)
     want = v.copy()
-    control_sets = [[0], [1], [2], [3], [4], [0, 3], [3, 6], [1, 2],
-                    [2, 9], [0, 1, 2, 3]]
+    control_sets = [[0], [1], [2], [3], [4], [5], [0, 3], [3, 6], [1, 2],
+                    [2, 9], [3, 4], [4, 7], [0, 1, 2, 3]]
     for cs in control_sets:
         free = [q for q in range(n) if q not in cs]
         for ts in (free[:k], free[-k:],
