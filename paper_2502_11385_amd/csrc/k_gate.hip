@@ -66,18 +66,20 @@ struct DenseArgs {
 //   keep, runs under 64 bytes: complex64 control on qubit 0, 1 or 2,
 //     3.46 -> 2.81; complex64 CZ on qubit 0, 1 or 2, 1.57 -> 1.40;
 //     complex128 CZ on qubit 0 or 1, 3.27 -> 2.90;
-//   skip: complex64 control on qubit 3, 3.05 -> 2.47, on qubit 4,
-//     1.70 -> 1.51; CZ on qubit 3 complex64, 1.21 -> 1.17; CZ on qubit 2 or 3
-//     complex128, 3.00 -> 2.62 and 1.55 -> 1.42.
-// Not taken: skip for a complex64 CZ on qubit 4 (0.77 -> 1.10), and testing
-// higher bits beside keep ones (complex128 CZ on qubits 1, 2: 6.26 -> 6.53),
-// so a gate with bits of both kinds has only its keep bits tested.  The
+//   skip: complex64 control on qubit 3, 2.75-3.00 -> 2.47-2.90 over
+//     targets 0 to 29; CZ on qubit 3 complex64, 1.21 -> 1.17; CZ on qubit 2
+//     or 3 complex128, 3.00 -> 2.62 and 1.55 -> 1.42.
+// Not taken: skip for a complex64 control on qubit 4 (target 29: 1.73 ->
+// 1.51, but targets 0, 8, 15: 1.46-1.58 -> 1.54-1.63) or 5, 6 (likewise
+// mixed), for a complex64 CZ on qubit 4 (0.77 -> 1.10), and testing higher
+// bits beside keep ones (complex128 CZ on qubits 1, 2: 6.26 -> 6.53), so a
+// gate with bits of both kinds has only its keep bits tested.  The
 // complex128 dense kernel keeps the plain walk: neither form gained there
 // (storing back made the compiler wait on each 16-byte store).
 struct LowBits {
   uint64_t keep, skip;
 };
-constexpr LowBits kDenseLowC64 = {0x7, 0x18};
+constexpr LowBits kDenseLowC64 = {0x7, 0x8};
 constexpr LowBits kDenseLowC128 = {0, 0};
 constexpr LowBits kDiagLowC64 = {0x7, 0x8};
 constexpr LowBits kDiagLowC128 = {0x3, 0xc};
