@@ -271,7 +271,9 @@ struct DiagArgs {
   double d[64];         // diagonal entries (re, im); masked: d[0..1] = phase
 };
 
-// Masked phase: multiply the amplitudes whose bits in fixed_mask are all 1.
+// Masked phase: multiply the amplitudes whose bits in fixed_mask and in
+// lowmask are all 1 (SKIP: a lane whose lowmask bits are not leaves its
+// amplitude alone; otherwise it stores it back unchanged).
 template <typename T, bool SKIP>
 __global__ void __launch_bounds__(256)
     diag_masked_kernel(typename CxT<T>::type* __restrict__ a, DiagArgs args) {
@@ -295,7 +297,8 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// General diagonal: multiply by d[r(i)] where controls are satisfied.
+// General diagonal: multiply by d[r(i)], r the target bits, where the
+// controls (fixed_mask and lowmask) are satisfied.
 template <typename T, bool SKIP>
 __global__ void __launch_bounds__(256)
     diag_table_kernel(typename CxT<T>::type* __restrict__ a, DiagArgs args) {
