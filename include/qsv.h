@@ -110,8 +110,11 @@ qsv_status qsv_init_basis(qsv_state s, uint64_t index);
  * This is the per-gate kernel of full-circuit execution (Section III.B,
  * gates u1/u3/CNOT of the cache-blocking example).  Gates on 4 or 5 targets
  * without controls run on the matrix cores (the matrix rounded once to FP32
- * for complex64 states); all others on the vector units.  Enqueued on the
- * state's stream; the matrix is copied before return. */
+ * for complex64 states); all others on the vector units.  Amplitudes
+ * outside the update keep their values, but a pass may store some of them
+ * back unchanged (controls on the lowest qubits), so no other stream may
+ * write the state's memory meanwhile.  Enqueued on the state's stream; the
+ * matrix is copied before return. */
 qsv_status qsv_apply_gate(qsv_state s, const int32_t* targets, int32_t k,
                           const int32_t* controls, int32_t c,
                           const double* matrix);
